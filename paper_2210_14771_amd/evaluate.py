@@ -1,0 +1,88 @@
+"""Normalised Hausdorff error of a content-area estimate (Section 2.3).
+
+Evaluation harness, not part of the estimator: it compares an estimated
+content area with the ground truth of a synthetic frame.
+
+The content area is the disc intersected with the sensor rectangle
+[-0.5, W-0.5] x [-0.5, H-0.5] in pixel-index coordinates, or the whole
+rectangle when there is no valid circle (Section 2.2.1).  Its edge is
+sampled every <= 0.1 px: the arcs of the circle inside the rectangle plus
+the rectangle's sides inside the disc.  H(A, B) = max(h(A, B), h(B, A)) with
+Euclidean distances (Eqs. 4-5), scaled by the ratio of the 1920x1080
+diagonal to the frame's diagonal (Eq. 6).  Misses and bad misses are errors
+above 15 px and 25 px.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+D_REF = math.hypot(1920.0, 1080.0)
+MISS_PX = 15.0
+BAD_MISS_PX = 25.0
+
+
+def edge_points(w: int, h: int, circle: tuple[float, float, float] | None,
+                spacing: float = 0.1) -> np.ndarray:
+    """Points along the edge of disc(circle) intersected with the frame rectangle."""
+    x0, x1, y0, y1 = -0.5, w - 0.5, -0.5, h - 0.5
+    sides = []
+    for (ax, ay, bx, by) in ((x0, y0, x1, y0), (x1, y0, x1, y1), (x1, y1, x0, y1),
+                             (x0, y1, x0, y0)):
+        n = int(math.ceil(math.hypot(bx - ax, by - ay) / spacing)) + 1
+        t = np.linspace(0.0, 1.0, n)
+        sides.append(np.stack([ax + t * (bx - ax), ay + t * (by - ay)], 1))
+    rect = np.concatenate(sides)
+    if circle is None:
+        return rect
+    cx, cy, r = circle
+    inside = np.hypot(rect[:, 0] - cx, rect[:, 1] - cy) <= r
+    n = int(math.ceil(2 * math.pi * r / spacing)) + 1
+    a = np.linspace(0.0, 2 * math.pi, n, endpoint=False)
+    arc = np.stack([cx + r * np.cos(a), cy + r * np.sin(a)], 1)
+    tol = 1e-9
+    keep = ((arc[:, 0] >= x0 - tol) & (arc[:, 0] <= x1 + tol) & (arc[:, 1] >= y0 - tol)
+            & (arc[:, 1] <= y1 + tol))
+    if not keep.any():
+        # disc covers the rectangle, or misses it entirely
+        return rect if inside.all() else arc
+    return np.concatenate([arc[keep], rect[inside]])
+
+
+def hausdorff(a: np.ndarray, b: np.ndarray) -> float:
+    da, _ = cKDTree(b).query(a)
+    db, _ = cKDTree(a).query(b)
+    return float(max(da.max(), db.max()))
+
+
+def normalised_hausdorff(w: int, h: int, gt: tuple[float, float, float] | None,
+                         est: tuple[float, float, float] | None) -> float:
+    """NH(A, B) = (d / d_I) H(A, B), d = 1920x1080 diagonal, d_I = frame diagonal."""
+    return hausdorff(edge_points(w, h, gt), edge_points(w, h, est)) * D_REF / math.hypot(w, h)
+
+
+def summarise(errors) -> dict:
+    e = np.asarray(errors, dtype=np.float64)
+    if e.size == 0:
+        return {}
+    return {
+        "mean_px": float(e.mean()),
+        "median_px": float(np.median(e)),
+        "p95_px": float(np.percentile(e, 95)),
+        "frac_le_2px": float((e <= 2.0).mean()),
+        "miss_pct": float(100.0 * (e > MISS_PX).mean()),
+        "bad_miss_pct": float(100.0 * (e > BAD_MISS_PX).mean()),
+        "n": int(e.size),
+    }
+
+
+def frame_errors(specs, cx, cy, r, valid) -> np.ndarray:
+    """Normalised Hausdorff error of each estimate against its FrameSpec."""
+    out = []
+    for i, s in enumerate(specs):
+        gt = (s.cx, s.cy, s.r) if s.has_border else None
+        est = (float(cx[i]), float(cy[i]), float(r[i])) if bool(valid[i]) else None
+        out.append(normalised_hausdorff(s.width, s.height, gt, est))
+    return np.asarray(out)

@@ -1,0 +1,217 @@
+"""Seeded synthetic endoscopic frames with a known content-area circle.
+
+Input generator only: this module draws pixels and ground truth and holds
+none of the estimator's arithmetic, so both the HIP path and the CPU oracle
+can be fed from it.  It stands in for the paper's annotated datasets
+(Section 2.1, Table 1), which are not available here.
+
+Image model (Section 1.1, Figure 1): a circular projection of the scope's
+field of view intersected with the sensor rectangle.  Inside the disc is a
+smooth tissue-like colour field; outside is a dark grey border with Gaussian
+noise.  The transition is an analytically Gaussian-blurred step, so the 50 %
+level sits exactly on the ground-truth radius.  Coordinates are pixel-index
+coordinates: pixel (x, y) has its centre at integer (x, y).
+
+Every frame is generated from its own ``numpy.random.SeedSequence`` built
+from ``(2210_14771, config_id, frame_idx)``, so any frame can be reproduced
+alone, independent of batch composition.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+from scipy.special import ndtr
+
+ROOT_SEED = 2210_14771
+
+KIND_PARTIAL = 0   # circle clipped by the sensor, at least one corner outside
+KIND_FULL = 1      # whole circle inside the sensor rectangle
+KIND_NOBORDER = 2  # no border at all: content fills the rectangle
+KIND_NAMES = {KIND_PARTIAL: "partial", KIND_FULL: "full", KIND_NOBORDER: "noborder"}
+
+
+@dataclasses.dataclass
+class FrameSpec:
+    """Drawn parameters of one synthetic frame (the ground truth)."""
+    width: int
+    height: int
+    kind: int
+    cx: float
+    cy: float
+    r: float
+    border_sigma: float
+    blur_sigma: float
+    vignette: float
+    mean_luma: float
+
+    @property
+    def has_border(self) -> bool:
+        return self.kind != KIND_NOBORDER
+
+
+def _interp_matrix(n_out: int, n_in: int) -> np.ndarray:
+    """Linear interpolation weights mapping n_in control values onto n_out samples."""
+    pos = np.linspace(0.0, n_in - 1.0, n_out)
+    i0 = np.clip(np.floor(pos).astype(np.int64), 0, n_in - 2)
+    f = pos - i0
+    m = np.zeros((n_out, n_in), dtype=np.float32)
+    m[np.arange(n_out), i0] = 1.0 - f
+    m[np.arange(n_out), i0 + 1] = f
+    return m
+
+
+def _smooth_field(rng: np.random.Generator, h: int, w: int, cell: float) -> np.ndarray:
+    """Zero-mean, roughly unit-variance smooth random field of shape (h, w)."""
+    gh = max(3, int(round(h / cell)) + 2)
+    gw = max(3, int(round(w / cell)) + 2)
+    g = rng.standard_normal((gh, gw), dtype=np.float32)
+    # two passes of a small box blur on the control grid soften the lattice
+    g = (g + np.roll(g, 1, 0) + np.roll(g, -1, 0)) / 3.0
+    g = (g + np.roll(g, 1, 1) + np.roll(g, -1, 1)) / 3.0
+    g /= max(float(g.std()), 1e-6)
+    return _interp_matrix(h, gh) @ g @ _interp_matrix(w, gw).T
+
+
+def _content(rng: np.random.Generator, spec: FrameSpec, rho: np.ndarray | None) -> np.ndarray:
+    """Tissue-like smooth colour field, float32 (H, W, 3), mean luma near spec.mean_luma."""
+    h, w = spec.height, spec.width
+    cell = max(h, w) / 10.0
+    base = _smooth_field(rng, h, w, cell)
+    fine = _smooth_field(rng, h, w, cell / 4.0)
+    lum = spec.mean_luma * (1.0 + 0.18 * base + 0.06 * fine)
+    # per-frame reddish tint; channel gains chosen so BT.601 luma of the gains is 1
+    tint = np.array([1.30, 0.88, 0.72], dtype=np.float32)
+    tint = tint * (1.0 + 0.05 * rng.standard_normal(3).astype(np.float32))
+    tint /= float(0.299 * tint[0] + 0.587 * tint[1] + 0.114 * tint[2])
+    chroma = [_smooth_field(rng, h, w, cell) for _ in range(3)]
+    img = np.empty((h, w, 3), dtype=np.float32)
+    for c in range(3):
+        img[..., c] = lum * np.float32(tint[c]) * (1.0 + np.float32(0.08) * chroma[c])
+    if spec.vignette > 0.0:
+        if rho is None:
+            yy, xx = np.mgrid[0:h, 0:w].astype(np.float32)
+            rho = np.hypot(xx - (w - 1) / 2.0, yy - (h - 1) / 2.0)
+            scale = float(np.hypot(w, h) / 2.0)
+        else:
+            scale = spec.r
+        fall = 1.0 - spec.vignette * np.minimum(rho / scale, 1.0) ** 2
+        img *= fall[..., None]
+    img += 2.0 * rng.standard_normal(img.shape, dtype=np.float32)
+    return img
+
+
+def render(spec: FrameSpec, rng: np.random.Generator) -> np.ndarray:
+    """Render one uint8 (H, W, 3) RGB frame for ``spec`` from ``rng``."""
+    h, w = spec.height, spec.width
+    if spec.kind == KIND_NOBORDER:
+        img = _content(rng, spec, None)
+        return np.clip(np.rint(img), 0, 255).astype(np.uint8)
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float32)
+    rho = np.hypot(xx - np.float32(spec.cx), yy - np.float32(spec.cy))
+    img = _content(rng, spec, rho)
+    alpha = ndtr((np.float32(spec.r) - rho) / np.float32(spec.blur_sigma)).astype(np.float32)
+    border = 6.0 + np.float32(spec.border_sigma) * rng.standard_normal((h, w), dtype=np.float32)
+    out = alpha[..., None] * img + (1.0 - alpha)[..., None] * border[..., None]
+    return np.clip(np.rint(out), 0, 255).astype(np.uint8)
+
+
+def _corners_outside(cx: float, cy: float, r: float, w: int, h: int) -> int:
+    corners = [(-0.5, -0.5), (w - 0.5, -0.5), (-0.5, h - 0.5), (w - 0.5, h - 0.5)]
+    return sum(1 for (x, y) in corners if np.hypot(x - cx, y - cy) > r)
+
+
+def draw_spec(rng: np.random.Generator, w: int, h: int, mix: tuple[float, float, float],
+              border_sigma: tuple[float, float], blur_sigma: tuple[float, float],
+              vignette: tuple[float, float], radius_frac: tuple[float, float] | None) -> FrameSpec:
+    """Draw the ground truth of one frame.
+
+    ``radius_frac`` fixes r ~ U(lo, hi) * H for every bordered frame (the
+    small 640x480 workload); when it is None the kind decides the radius:
+    partial circles r ~ U(0.55, 0.95) * H with at least one corner outside
+    the disc, full circles r ~ U(0.30 H, distance to the nearest edge - 3 blur).
+    """
+    p = np.asarray(mix, dtype=np.float64)
+    kind = int(rng.choice(3, p=p / p.sum()))
+    bs = float(rng.uniform(*border_sigma))
+    bl = float(rng.uniform(*blur_sigma))
+    vg = float(rng.uniform(*vignette))
+    luma = float(rng.uniform(90.0, 150.0))
+    for _ in range(1000):
+        cx = (w - 1) / 2.0 + float(rng.uniform(-0.08, 0.08)) * w
+        cy = (h - 1) / 2.0 + float(rng.uniform(-0.08, 0.08)) * h
+        if kind == KIND_NOBORDER:
+            r = float(np.hypot(w, h))
+            break
+        if radius_frac is not None:
+            r = float(rng.uniform(*radius_frac)) * h
+            inside = min(cx + 0.5, w - 0.5 - cx, cy + 0.5, h - 0.5 - cy) >= r
+            kind = KIND_FULL if inside else KIND_PARTIAL
+            break
+        if kind == KIND_PARTIAL:
+            r = float(rng.uniform(0.55, 0.95)) * h
+            if _corners_outside(cx, cy, r, w, h) >= 1:
+                break
+        else:
+            rmax = min(cx + 0.5, w - 0.5 - cx, cy + 0.5, h - 0.5 - cy) - 3.0 * bl
+            if rmax > 0.30 * h:
+                r = float(rng.uniform(0.30 * h, rmax))
+                break
+    else:  # pragma: no cover - the rejection loop accepts within a few draws
+        raise RuntimeError("could not draw a frame spec")
+    return FrameSpec(w, h, kind, cx, cy, r, bs, bl, vg, luma)
+
+
+@dataclasses.dataclass
+class Workload:
+    """Shape and distribution of one synthetic workload."""
+    config_id: int
+    width: int
+    height: int
+    n_frames: int
+    mix: tuple[float, float, float]
+    border_sigma: tuple[float, float]
+    blur_sigma: tuple[float, float]
+    vignette: tuple[float, float]
+    radius_frac: tuple[float, float] | None
+    n_hstrips: int
+    n_vstrips: int
+    attempts: int
+
+
+# Small case: 8 x 640x480, every frame bordered, r ~ U(0.45, 0.75) H,
+# border sigma 3, edge blur 1.5 px; 16+16 strips, 256 RANSAC attempts.
+SMALL_640x480 = Workload(1, 640, 480, 8, (1.0, 0.0, 0.0), (3.0, 3.0), (1.5, 1.5), (0.0, 0.0),
+                         (0.45, 0.75), 16, 16, 256)
+# Headline case: 64 x 1920x1080, partial : full : no border = 60 : 25 : 10 (renormalised),
+# border sigma U(2, 8), blur U(1, 3), vignetting up to 40 %; 32+32 strips, 1024 attempts.
+HD_1080p = Workload(2, 1920, 1080, 64, (60.0, 25.0, 10.0), (2.0, 8.0), (1.0, 3.0), (0.0, 0.4),
+                    None, 32, 32, 1024)
+WORKLOADS = {1: SMALL_640x480, 2: HD_1080p}
+
+
+def frame_rng(config_id: int, frame_idx: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([ROOT_SEED, config_id, frame_idx]))
+
+
+def make_frame(wl: Workload, frame_idx: int, width: int | None = None,
+               height: int | None = None) -> tuple[np.ndarray, FrameSpec]:
+    """Frame ``frame_idx`` of workload ``wl`` (optionally at another resolution)."""
+    rng = frame_rng(wl.config_id, frame_idx)
+    w = wl.width if width is None else width
+    h = wl.height if height is None else height
+    spec = draw_spec(rng, w, h, wl.mix, wl.border_sigma, wl.blur_sigma, wl.vignette,
+                     wl.radius_frac)
+    return render(spec, rng), spec
+
+
+def make_batch(wl: Workload, n_frames: int | None = None, start: int = 0,
+               width: int | None = None, height: int | None = None
+               ) -> tuple[np.ndarray, list[FrameSpec]]:
+    """uint8 [B, H, W, 3] batch of frames start .. start+B-1 and their specs."""
+    n = wl.n_frames if n_frames is None else n_frames
+    frames, specs = [], []
+    for i in range(start, start + n):
+        f, s = make_frame(wl, i, width, height)
+        frames.append(f)
+        specs.append(s)
+    return np.stack(frames), specs

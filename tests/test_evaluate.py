@@ -1,0 +1,49 @@
+"""Pins of the normalised Hausdorff evaluation harness (Section 2.3, Eqs. 4-6)."""
+import math
+
+import numpy as np
+from scipy.spatial.distance import directed_hausdorff
+
+from paper_2210_14771_amd import evaluate as ev
+
+
+def test_two_full_circles_closed_form():
+    # for two circles fully inside the frame, H = |dc| + |dr|
+    w, h = 1920, 1080
+    for (c1, c2) in [((960, 540, 400), (963, 544, 410)), ((900, 500, 300), (900, 500, 305)),
+                     ((1000, 600, 350), (990, 590, 350))]:
+        d = math.hypot(c1[0] - c2[0], c1[1] - c2[1]) + abs(c1[2] - c2[2])
+        got = ev.normalised_hausdorff(w, h, c1, c2)
+        assert abs(got - d) < 0.06
+
+
+def test_identical_and_rectangles():
+    assert ev.normalised_hausdorff(640, 480, None, None) == 0.0
+    assert ev.normalised_hausdorff(640, 480, (320, 240, 250), (320, 240, 250)) == 0.0
+
+
+def test_matches_scipy_directed_hausdorff():
+    a = ev.edge_points(640, 480, (300, 250, 280))
+    b = ev.edge_points(640, 480, (330, 230, 300))
+    ref = max(directed_hausdorff(a, b)[0], directed_hausdorff(b, a)[0])
+    assert abs(ev.hausdorff(a, b) - ref) < 1e-9
+
+
+def test_normalisation_eq6():
+    # 640x480 frame: 1 native px counts as 2202.9 / 800 normalised px
+    got = ev.normalised_hausdorff(640, 480, (320, 240, 100), (320, 240, 101))
+    assert abs(got - 2202.907 / 800.0) < 0.2
+
+
+def test_clipped_circle_edges():
+    # a partial circle: its edge includes the rectangle sides inside the disc
+    pts = ev.edge_points(1920, 1080, (960, 540, 1000))
+    assert np.any(np.isclose(pts[:, 1], -0.5)) and np.any(np.isclose(pts[:, 0], -0.5))
+    # disc covering the whole frame equals the rectangle
+    big = ev.normalised_hausdorff(1920, 1080, (960, 540, 5000), None)
+    assert big == 0.0
+
+
+def test_summary():
+    s = ev.summarise([1.0, 3.0, 20.0, 30.0])
+    assert s["frac_le_2px"] == 0.25 and s["miss_pct"] == 50.0 and s["bad_miss_pct"] == 25.0
