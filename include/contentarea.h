@@ -1,0 +1,199 @@
+/*
+ * contentarea.h -- C ABI of the MI355X (gfx950) endoscopic content-area
+ * estimator.
+ *
+ * The method is the "lean GPU-based pipeline" of Budd et al., arXiv
+ * 2210.14771, Section 2.2: sample horizontal (and here also vertical) strips
+ * of each RGB frame (Section 2.2.2, Eq. 1), score every pixel of each half
+ * strip from its Sobel gradient magnitude, the angle between the gradient
+ * and the direction to the image centre and the maximum intensity preceding
+ * it (Section 2.2.3, Eqs. 2-3), keep the best pixel of each half strip,
+ * filter, and fit a circle by RANSAC over point triples with least-squares
+ * refits (Section 2.2.5).  The result per frame is a circle, or "no circle":
+ * the content area is then the whole frame (Section 2.2.1).
+ *
+ * Conventions
+ *   - Frames are 8-bit RGB, channel-interleaved (R, G, B per pixel), rows
+ *     `row_stride` bytes apart.  Coordinates are pixel indices: pixel
+ *     (x, y) has its centre at (x, y); +x right, +y down.
+ *   - Device pointers are HIP device memory of the context's device.  The
+ *     library only reads `frames_dev` and only writes the output array.
+ *   - `stream` is a hipStream_t (NULL: the legacy default stream).  Every
+ *     call only enqueues work: results are ready when the stream has
+ *     completed it.  The caller keeps the frames and outputs alive until then.
+ *   - Every entry point returns CA_OK (0) or a negative CA_E_* code and never
+ *     throws.  Argument errors are detected before anything is enqueued.
+ *     Device faults surface at the caller's next stream synchronisation.
+ *   - A context is not thread-safe: use one context per host thread.
+ *     Calls on one context may target different streams; the context
+ *     serialises its own scratch use by enqueuing on the given stream, so
+ *     calls on two different streams of one context must not overlap.
+ */
+#ifndef CONTENTAREA_H
+#define CONTENTAREA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CA_OK 0
+#define CA_E_INVAL (-1)        /* null pointer or argument out of range */
+#define CA_E_UNSUPPORTED (-2)  /* layout the library does not handle (pixel_stride != 3) */
+#define CA_E_NOMEM (-3)        /* workspace budget of the context exceeded */
+#define CA_E_DEVICE (-4)       /* a HIP runtime call failed */
+
+#define CA_MAX_STRIPS 64       /* per direction */
+#define CA_MAX_ATTEMPTS 4096
+#define CA_MAX_EXTENT 16384    /* largest width or height */
+
+/* Opaque context: device, cached strip tables and score tables, workspace. */
+typedef struct ca_ctx ca_ctx;
+
+/* One frame of a batch (32 bytes). */
+typedef struct {
+    int32_t width, height;   /* pixels, each in [16, CA_MAX_EXTENT] */
+    int32_t row_stride;      /* bytes between the starts of two rows, >= 3 * width */
+    int32_t pixel_stride;    /* bytes between pixels; must be 3 */
+    int64_t byte_offset;     /* first byte of the frame relative to `frames_dev`, >= 0 */
+    uint64_t frame_uid;      /* identifies the frame to the RANSAC sampler: the
+                                triples depend on (seed, frame_uid, attempt) only,
+                                never on the frame's position in the batch */
+} ca_frame_desc;
+
+/* Parameters: Appendix A, Table A1, plus the vertical strips, the RANSAC
+ * attempt count and the sampler.  Get the paper's values from
+ * ca_default_params() and override fields. */
+typedef struct {
+    int32_t n_hstrips;       /* N horizontal strips, Eq. 1 (16) */
+    int32_t n_vstrips;       /* vertical strips along the width (16; 0 = paper-literal) */
+    double alpha;            /* strip weighting toward the frame edges, Eq. 1 (8) */
+    double t_g;              /* gradient magnitude soft threshold, Eq. 2 (20) */
+    double t_theta_deg;      /* gradient direction soft threshold in degrees, Eq. 2 (30) */
+    double t_iota;           /* preceding maximum intensity soft threshold, Eq. 2 (25) */
+    double t_ps;             /* point score threshold (0.03), compared in float32 */
+    double t_cs;             /* circle score threshold (0.06) on sum(inlier scores) / P */
+    int32_t t_px;            /* candidates closer than this to the frame edge are dropped (3) */
+    int32_t refine_iters;    /* least-squares refits per attempt (3) */
+    double t_ri;             /* inlier distance in pixels (3) */
+    double r_min, r_max;     /* radius limits, multiples of the width (0.1, 0.8) */
+    double d_max;            /* centre offset limit, multiple of the width (0.2) */
+    int32_t ransac_attempts; /* attempts per frame, [1, CA_MAX_ATTEMPTS] (256) */
+    int32_t sampler;         /* 0 random triples; 1 the a-th triple in lexicographic order */
+    uint64_t seed;           /* key of the counter-based sampler */
+} ca_params;
+
+/* Result per frame (32 bytes). */
+typedef struct {
+    float cx, cy, r;         /* best circle, pixel-index coordinates (0 if none) */
+    float score;             /* sum of the circle's inlier scores / P, P = 2 (n_hstrips + n_vstrips) */
+    int32_t inliers;         /* inliers of the best circle */
+    int32_t n_points;        /* candidate points kept after filtering */
+    int32_t valid;           /* 1: content area = disc within the frame; 0: whole frame */
+    int32_t reason;          /* 0 valid, 1 fewer than 3 points, 2 no attempt within the
+                                radius and centre limits, 3 best score below t_cs */
+} ca_result;
+
+/* Best pixel of one half strip (8 bytes).  Frame f's P candidates are
+ * stored at [f * P, (f + 1) * P) in canonical order: horizontal strip i
+ * gives 2i (left half) and 2i+1 (right half); vertical strip j gives
+ * 2 n_hstrips + 2j (top) and 2 n_hstrips + 2j + 1 (bottom). */
+typedef struct {
+    int16_t x, y;
+    float score;             /* s = s_g s_theta s_iota, Eq. 3 */
+} ca_point;
+
+/* One RANSAC attempt (56 bytes), for tests. */
+typedef struct {
+    int32_t status;          /* 0 degenerate, 1 outside the radius/centre limits, 2 kept */
+    int32_t fail_stage;      /* status 0: 0 collinear triple, k refit k had < 3 inliers
+                                or a singular system, -1 no triple (enumeration exhausted) */
+    int32_t i0, i1, i2;      /* triple, indices into the kept points (canonical order) */
+    int32_t inliers;         /* inliers of the final circle */
+    uint64_t qsum;           /* sum over those inliers of floor(score * 2^24) */
+    double cx, cy, r2;       /* final circle: centre and squared radius */
+} ca_attempt;
+
+/* Fill `p` with the paper's defaults (Table A1); 16 + 16 strips, 256 random
+ * attempts, seed 0. */
+void ca_default_params(ca_params *p);
+
+/* Create a context on HIP device `device`.  `workspace_budget_bytes` caps the
+ * device memory the context may hold for tables and scratch (0 = 1 GiB).
+ * Returns CA_E_INVAL for a null `ctx` or a bad device, CA_E_DEVICE if HIP
+ * fails. */
+int ca_create(ca_ctx **ctx, int device, size_t workspace_budget_bytes);
+
+/* Release everything the context holds.  Synchronises the device first.
+ * Null is ignored. */
+void ca_destroy(ca_ctx *ctx);
+
+/* Estimate the content area of `n_frames` frames (Section 2.2).
+ *   frames_dev  device base address of the frames (read only)
+ *   dims_host   host array of n_frames descriptors (copied during the call)
+ *   params      host pointer (copied during the call); NULL = defaults
+ *   out_dev     device array of n_frames results (written by the stream)
+ * n_frames = 0 is a no-op.  Errors: CA_E_INVAL (null pointer, size or
+ * parameter out of range), CA_E_UNSUPPORTED (pixel_stride != 3), CA_E_NOMEM
+ * (budget too small for this batch; the context stays usable), CA_E_DEVICE. */
+int ca_estimate_area(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
+                     int32_t n_frames, const ca_params *params, ca_result *out_dev,
+                     void *stream);
+
+/* The same pipeline, additionally writing every frame's P candidates
+ * (Section 2.2.5, first sentence) to `points_dev` (n_frames * P entries). */
+int ca_debug_candidates(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
+                        int32_t n_frames, const ca_params *params, ca_point *points_dev,
+                        ca_result *out_dev, void *stream);
+
+/* The same pipeline, additionally writing every RANSAC attempt
+ * (n_frames * ransac_attempts records, frame-major) to `attempts_dev`.
+ * Frames with fewer than 3 kept points get all-zero records. */
+int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
+                      int32_t n_frames, const ca_params *params, ca_attempt *attempts_dev,
+                      ca_result *out_dev, void *stream);
+
+/* Host-side helpers (no device work). */
+
+/* The argument checks ca_estimate_area applies before enqueuing anything:
+ * CA_OK, CA_E_INVAL or CA_E_UNSUPPORTED.  `params` NULL = defaults. */
+int ca_check_args(const ca_frame_desc *dims_host, int32_t n_frames, const ca_params *params);
+
+/* Eq. 1 positions of n strips along an axis of `extent` pixels: floor, then
+ * clamped to [1, extent - 2].  Returns CA_E_INVAL for extent < 3 or n < 0. */
+int ca_strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos);
+
+/* Score tables of Eq. 2 as the kernels use them: sg[q] = tanh(q / (8 t_g))
+ * for q < *sg_len (the table stops at the first entry equal to 1.0f; larger
+ * indices read the last entry), st[q] = 1 - tanh(theta_q / t_theta) for the
+ * 2049 pseudo-angle bins, si[i] = 1 - tanh(i / t_iota) for 256 levels.
+ * `sg` must hold CA_SG_CAPACITY floats; `sg_len` receives the used length. */
+#define CA_SG_CAPACITY 11541
+int ca_score_tables(const ca_params *p, float *sg, int32_t *sg_len, float *st, float *si);
+
+/* Kernel timing (HIP events recorded on the caller's stream around each
+ * kernel of each call).  Index 0: strip scoring, 1: RANSAC, 2: selection. */
+typedef struct {
+    double total_ms[3];      /* summed kernel durations */
+    int64_t launches[3];     /* number of timed launches */
+} ca_kernel_times;
+
+/* Start timing the next `max_calls` estimate calls of this context (events
+ * are created here, none during the calls).  CA_E_INVAL for max_calls < 1. */
+int ca_profile_begin(ca_ctx *ctx, int32_t max_calls);
+
+/* Wait for the timed calls, write their totals and release the events. */
+int ca_profile_end(ca_ctx *ctx, ca_kernel_times *out);
+
+/* Static description of a return code. */
+const char *ca_error_string(int code);
+
+/* Library version string. */
+const char *ca_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in include/contentarea.h.
+
+Argument marshalling only.  The shared library is built in-tree by
+``paper_2210_14771_amd.build``; if it is missing this module raises instead
+of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+from .build import LIB_PATH
+
+CA_OK = 0
+CA_E_INVAL = -1
+CA_E_UNSUPPORTED = -2
+CA_E_NOMEM = -3
+CA_E_DEVICE = -4
+CA_MAX_STRIPS = 64
+CA_MAX_ATTEMPTS = 4096
+CA_MAX_EXTENT = 16384
+CA_SG_CAPACITY = 11541
+
+EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
+           "ca_debug_candidates", "ca_debug_attempts", "ca_check_args", "ca_strip_positions",
+           "ca_score_tables", "ca_profile_begin", "ca_profile_end", "ca_error_string",
+           "ca_version")
+
+
+class FrameDesc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("row_stride", C.c_int32),
+                ("pixel_stride", C.c_int32), ("byte_offset", C.c_int64),
+                ("frame_uid", C.c_uint64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("n_hstrips", C.c_int32), ("n_vstrips", C.c_int32), ("alpha", C.c_double),
+                ("t_g", C.c_double), ("t_theta_deg", C.c_double), ("t_iota", C.c_double),
+                ("t_ps", C.c_double), ("t_cs", C.c_double), ("t_px", C.c_int32),
+                ("refine_iters", C.c_int32), ("t_ri", C.c_double), ("r_min", C.c_double),
+                ("r_max", C.c_double), ("d_max", C.c_double), ("ransac_attempts", C.c_int32),
+                ("sampler", C.c_int32), ("seed", C.c_uint64)]
+
+
+class ResultRec(C.Structure):
+    _fields_ = [("cx", C.c_float), ("cy", C.c_float), ("r", C.c_float), ("score", C.c_float),
+                ("inliers", C.c_int32), ("n_points", C.c_int32), ("valid", C.c_int32),
+                ("reason", C.c_int32)]
+
+
+class PointRec(C.Structure):
+    _fields_ = [("x", C.c_int16), ("y", C.c_int16), ("score", C.c_float)]
+
+
+class AttemptRec(C.Structure):
+    _fields_ = [("status", C.c_int32), ("fail_stage", C.c_int32), ("i0", C.c_int32),
+                ("i1", C.c_int32), ("i2", C.c_int32), ("inliers", C.c_int32),
+                ("qsum", C.c_uint64), ("cx", C.c_double), ("cy", C.c_double),
+                ("r2", C.c_double)]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("total_ms", C.c_double * 3), ("launches", C.c_int64 * 3)]
+
+
+assert C.sizeof(FrameDesc) == 32 and C.sizeof(ResultRec) == 32
+assert C.sizeof(PointRec) == 8 and C.sizeof(AttemptRec) == 56
+
+_lib = None
+
+
+class NativeError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        msg = lib().ca_error_string(code).decode()
+        super().__init__(f"{what} failed: {msg} ({code})")
+        self.code = code
+
+
+def lib() -> C.CDLL:
+    """Load libcontentarea.so (built beforehand by ``build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2210_14771_amd.build.build() "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.ca_default_params.argtypes = [C.POINTER(Params)]
+        L.ca_default_params.restype = None
+        L.ca_create.argtypes = [C.POINTER(vp), C.c_int, C.c_size_t]
+        L.ca_destroy.argtypes = [vp]
+        L.ca_destroy.restype = None
+        run_args = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params)]
+        L.ca_estimate_area.argtypes = run_args + [vp, vp]
+        L.ca_debug_candidates.argtypes = run_args + [vp, vp, vp]
+        L.ca_debug_attempts.argtypes = run_args + [vp, vp, vp]
+        L.ca_check_args.argtypes = [C.POINTER(FrameDesc), i32, C.POINTER(Params)]
+        L.ca_strip_positions.argtypes = [i32, i32, C.c_double, C.POINTER(C.c_int32)]
+        L.ca_score_tables.argtypes = [C.POINTER(Params), C.POINTER(C.c_float),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_float),
+                                      C.POINTER(C.c_float)]
+        L.ca_profile_begin.argtypes = [vp, i32]
+        L.ca_profile_end.argtypes = [vp, C.POINTER(KernelTimes)]
+        L.ca_error_string.argtypes = [C.c_int]
+        L.ca_error_string.restype = C.c_char_p
+        L.ca_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(code: int, what: str) -> None:
+    if code != CA_OK:
+        raise NativeError(code, what)

@@ -1,0 +1,258 @@
+"""Python binding of the content-area estimator (argument marshalling only).
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+estimate runs in the library's gfx950 kernels behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Sequence
+
+import torch
+
+from . import _native as N
+
+
+def default_params(**overrides) -> N.Params:
+    """Table A1 defaults (ca_default_params) with keyword overrides."""
+    p = N.Params()
+    N.lib().ca_default_params(C.byref(p))
+    for k, v in overrides.items():
+        if k == "attempts":
+            k = "ransac_attempts"
+        if not any(k == f for f, _ in N.Params._fields_):
+            raise KeyError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def _as_params(params) -> N.Params:
+    if params is None:
+        return default_params()
+    if isinstance(params, N.Params):
+        return params
+    if isinstance(params, dict):
+        return default_params(**params)
+    raise TypeError("params must be None, a dict or a Params")
+
+
+@dataclasses.dataclass
+class Result:
+    """Per-frame estimates (device tensors of length B)."""
+    raw: torch.Tensor  # int32 [B, 8], one ca_result per row
+
+    @property
+    def cx(self) -> torch.Tensor:
+        return self.raw[:, 0].view(torch.float32)
+
+    @property
+    def cy(self) -> torch.Tensor:
+        return self.raw[:, 1].view(torch.float32)
+
+    @property
+    def r(self) -> torch.Tensor:
+        return self.raw[:, 2].view(torch.float32)
+
+    @property
+    def score(self) -> torch.Tensor:
+        return self.raw[:, 3].view(torch.float32)
+
+    @property
+    def inliers(self) -> torch.Tensor:
+        return self.raw[:, 4]
+
+    @property
+    def n_points(self) -> torch.Tensor:
+        return self.raw[:, 5]
+
+    @property
+    def valid(self) -> torch.Tensor:
+        return self.raw[:, 6] != 0
+
+    @property
+    def reason(self) -> torch.Tensor:
+        return self.raw[:, 7]
+
+    def numpy(self):
+        import numpy as np
+        dt = np.dtype([("cx", "<f4"), ("cy", "<f4"), ("r", "<f4"), ("score", "<f4"),
+                       ("inliers", "<i4"), ("n_points", "<i4"), ("valid", "<i4"),
+                       ("reason", "<i4")])
+        return self.raw.cpu().numpy().view(dt).reshape(-1)
+
+
+def _frames_layout(frames, frame_uids):
+    """(base pointer, FrameDesc array, n, device) for a [B,H,W,3] tensor or a
+    list of [H,W,3] tensors (mixed resolutions) on one device."""
+    if isinstance(frames, torch.Tensor):
+        if frames.dim() == 3:
+            frames = frames.unsqueeze(0)
+        if frames.dim() != 4 or frames.shape[-1] != 3:
+            raise ValueError("frames must be uint8 [B, H, W, 3]")
+        items = [frames[i] for i in range(frames.shape[0])]
+        dev = frames.device
+    else:
+        items = list(frames)
+        if not items:
+            raise ValueError("empty frame list")
+        dev = items[0].device
+    for t in items:
+        if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[-1] != 3:
+            raise ValueError("each frame must be uint8 [H, W, 3]")
+        if t.device != dev or dev.type != "cuda":
+            raise ValueError("frames must all be on one GPU")
+        if t.stride(2) != 1 or t.stride(1) != 3:
+            raise ValueError("pixels must be packed RGB (stride 3 along W, 1 along channels)")
+    n = len(items)
+    if frame_uids is None:
+        uids = list(range(n))
+    else:
+        uids = [int(u) for u in frame_uids]
+        if len(uids) != n:
+            raise ValueError("frame_uids must have one entry per frame")
+    base = min(t.data_ptr() for t in items)
+    descs = (N.FrameDesc * n)()
+    for i, t in enumerate(items):
+        d = descs[i]
+        d.width, d.height = t.shape[1], t.shape[0]
+        d.row_stride = t.stride(0)
+        d.pixel_stride = 3
+        d.byte_offset = t.data_ptr() - base
+        d.frame_uid = uids[i] & 0xFFFFFFFFFFFFFFFF
+    return base, descs, n, dev
+
+
+class Estimator:
+    """One library context on one GPU (not thread-safe: one per host thread)."""
+
+    def __init__(self, device=None, workspace_budget: int = 1 << 30):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the content-area estimator needs a HIP GPU")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        ctx = C.c_void_p()
+        N.check(N.lib().ca_create(C.byref(ctx), self.device.index, workspace_budget),
+                "ca_create")
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            N.lib().ca_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile_begin(self, max_calls: int) -> None:
+        """Time each kernel of the next ``max_calls`` calls with HIP events."""
+        N.check(N.lib().ca_profile_begin(self._ctx, max_calls), "ca_profile_begin")
+
+    def profile_end(self) -> dict:
+        """Average kernel durations (ms) of the calls timed since profile_begin."""
+        t = N.KernelTimes()
+        N.check(N.lib().ca_profile_end(self._ctx, C.byref(t)), "ca_profile_end")
+        names = ("strips", "ransac", "select")
+        return {n: {"total_ms": t.total_ms[i], "launches": int(t.launches[i]),
+                    "avg_ms": t.total_ms[i] / t.launches[i] if t.launches[i] else 0.0}
+                for i, n in enumerate(names)}
+
+    def _prep(self, frames, params, frame_uids, stream):
+        base, descs, n, dev = _frames_layout(frames, frame_uids)
+        if dev.index != self.device.index:
+            raise ValueError(f"frames on {dev}, estimator on {self.device}")
+        p = _as_params(params)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return base, descs, n, p, s
+
+    def estimate_area(self, frames, params=None, frame_uids: Sequence[int] | None = None,
+                      out: torch.Tensor | None = None, stream=None) -> Result:
+        """Content area of each frame (Section 2.2); enqueued on the current stream."""
+        base, descs, n, p, s = self._prep(frames, params, frame_uids, stream)
+        if out is None:
+            out = torch.empty((n, 8), dtype=torch.int32, device=self.device)
+        rc = N.lib().ca_estimate_area(self._ctx, C.c_void_p(base), descs, n, C.byref(p),
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream))
+        N.check(rc, "ca_estimate_area")
+        return Result(out)
+
+    def debug_candidates(self, frames, params=None, frame_uids=None, stream=None):
+        """(Result, points int16/float32 packed as int32 [B, P, 2])."""
+        base, descs, n, p, s = self._prep(frames, params, frame_uids, stream)
+        P = 2 * (p.n_hstrips + p.n_vstrips)
+        out = torch.empty((n, 8), dtype=torch.int32, device=self.device)
+        pts = torch.empty((n, P, 2), dtype=torch.int32, device=self.device)
+        rc = N.lib().ca_debug_candidates(self._ctx, C.c_void_p(base), descs, n, C.byref(p),
+                                         C.c_void_p(pts.data_ptr()), C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(s.cuda_stream))
+        N.check(rc, "ca_debug_candidates")
+        return Result(out), pts
+
+    def debug_attempts(self, frames, params=None, frame_uids=None, stream=None):
+        """(Result, attempts as raw bytes uint8 [B, A, 56])."""
+        base, descs, n, p, s = self._prep(frames, params, frame_uids, stream)
+        A = p.ransac_attempts
+        out = torch.empty((n, 8), dtype=torch.int32, device=self.device)
+        att = torch.empty((n, A, 56), dtype=torch.uint8, device=self.device)
+        rc = N.lib().ca_debug_attempts(self._ctx, C.c_void_p(base), descs, n, C.byref(p),
+                                       C.c_void_p(att.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       C.c_void_p(s.cuda_stream))
+        N.check(rc, "ca_debug_attempts")
+        return Result(out), att
+
+
+POINT_FIELDS = [("x", "<i2"), ("y", "<i2"), ("score", "<f4")]
+ATTEMPT_FIELDS = [("status", "<i4"), ("fail_stage", "<i4"), ("i0", "<i4"), ("i1", "<i4"),
+                  ("i2", "<i4"), ("inliers", "<i4"), ("qsum", "<u8"), ("cx", "<f8"),
+                  ("cy", "<f8"), ("r2", "<f8")]
+
+
+def points_numpy(pts: torch.Tensor):
+    """Structured numpy view (x, y, score) of debug_candidates' points."""
+    import numpy as np
+    a = pts.cpu().contiguous().numpy()
+    return a.view(np.dtype(POINT_FIELDS)).reshape(a.shape[0], a.shape[1])
+
+
+def attempts_numpy(att: torch.Tensor):
+    import numpy as np
+    a = att.cpu().contiguous().numpy()
+    return a.view(np.dtype(ATTEMPT_FIELDS)).reshape(a.shape[0], a.shape[1])
+
+
+_default: dict[int, Estimator] = {}
+
+
+def estimate_area(frames, params=None, frame_uids=None) -> Result:
+    """Module-level convenience: one cached Estimator per device."""
+    dev = frames.device.index if isinstance(frames, torch.Tensor) else frames[0].device.index
+    est = _default.get(dev)
+    if est is None:
+        est = _default[dev] = Estimator(dev)
+    return est.estimate_area(frames, params, frame_uids)
+
+
+def strip_positions(extent: int, n: int, alpha: float = 8.0):
+    import numpy as np
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    N.check(N.lib().ca_strip_positions(extent, n, alpha,
+                                       out.ctypes.data_as(C.POINTER(C.c_int32))),
+            "ca_strip_positions")
+    return out[:n]
+
+
+def score_tables(params=None):
+    """(SG[:sg_len], ST, SI) float32 tables exactly as the kernels use them."""
+    import numpy as np
+    p = _as_params(params)
+    sg = np.zeros(N.CA_SG_CAPACITY, dtype=np.float32)
+    st = np.zeros(2049, dtype=np.float32)
+    si = np.zeros(256, dtype=np.float32)
+    n = C.c_int32()
+    f = lambda a: a.ctypes.data_as(C.POINTER(C.c_float))  # noqa: E731
+    N.check(N.lib().ca_score_tables(C.byref(p), f(sg), C.byref(n), f(st), f(si)),
+            "ca_score_tables")
+    return sg[:n.value], st, si

@@ -1,0 +1,589 @@
+// Host core of the content-area estimator: the C ABI declared in
+// include/contentarea.h.  Validates arguments, builds and caches per-batch
+// plans (strip positions of Eq. 1, the score tables of Eq. 2, scratch
+// buffers) in device memory, and enqueues the three kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ca_internal.h"
+
+namespace {
+
+using ca::FrameDev;
+using ca::Record;
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------- tables -----
+
+int strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos)
+{
+    // Eq. 1: h_i = extent / (1 + exp(-(alpha / N)(i - (N - 1) / 2)))
+    if (extent < 3 || n < 0)
+        return CA_E_INVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        const double t = (alpha / (double)n) * ((double)i - (double)(n - 1) / 2.0);
+        const double h = (double)extent / (1.0 + std::exp(-t));
+        int32_t p = (int32_t)std::floor(h);
+        p = p < 1 ? 1 : p;
+        p = p > extent - 2 ? extent - 2 : p;
+        pos[i] = p;
+    }
+    return CA_OK;
+}
+
+int score_tables(const ca_params &p, float *sg, int32_t *sg_len, float *st, float *si)
+{
+    // s_g = tanh(|g| / t_g) at |g| = q / 8; the table ends at its first 1.0f
+    int32_t n = 0;
+    for (int32_t q = 0; q < CA_SG_CAPACITY; ++q) {
+        const float v = (float)std::tanh((double)q / (8.0 * p.t_g));
+        sg[q] = v;
+        n = q + 1;
+        if (v == 1.0f)
+            break;
+    }
+    *sg_len = n;
+    // s_theta = 1 - tanh(theta_q / t_theta): theta_q is the lower edge of
+    // pseudo-angle bin q (u = q / 1024 = |c x g| / (|c x g| + c.g) below 90 deg)
+    for (int32_t q = 0; q < ca::kQtBins; ++q) {
+        const double u = (double)q / 1024.0;
+        const double th = u <= 1.0 ? std::atan2(u, 1.0 - u) : kPi - std::atan2(2.0 - u, u - 1.0);
+        st[q] = (float)(1.0 - std::tanh(th * (180.0 / kPi) / p.t_theta_deg));
+    }
+    // s_iota = 1 - tanh(iota / t_iota)
+    for (int32_t i = 0; i < ca::kLumaLevels; ++i)
+        si[i] = (float)(1.0 - std::tanh((double)i / p.t_iota));
+    return CA_OK;
+}
+
+// --------------------------------------------------------------- plans ----
+
+struct Shape {
+    int32_t W, H;
+};
+
+struct Plan {
+    // cache key
+    std::vector<ca_frame_desc> dims;
+    int32_t n_h = 0, n_v = 0, attempts = 0;
+    double alpha = 0, t_g = 0, t_theta = 0, t_iota = 0;
+    // device buffers (one allocation)
+    void *mem = nullptr;
+    size_t bytes = 0;
+    FrameDev *fd = nullptr;
+    int32_t *strips = nullptr;
+    float *lut = nullptr;
+    ca_point *cand = nullptr;
+    Record *rec = nullptr;
+    // launch facts
+    int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
+    bool rows_aligned = false;  // every row offset a multiple of 16
+    size_t lds = 0;
+    uint64_t last_use = 0;
+};
+
+bool same_key(const Plan &pl, const ca_frame_desc *dims, int32_t n, const ca_params &p)
+{
+    return pl.n_frames == n && pl.n_h == p.n_hstrips && pl.n_v == p.n_vstrips
+           && pl.attempts == p.ransac_attempts && pl.alpha == p.alpha && pl.t_g == p.t_g
+           && pl.t_theta == p.t_theta_deg && pl.t_iota == p.t_iota
+           && std::memcmp(pl.dims.data(), dims, sizeof(ca_frame_desc) * (size_t)n) == 0;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct ca_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    size_t max_lds = 0;
+    uint64_t tick = 0;
+    std::vector<Plan *> plans;
+    // kernel timing: 4 events per timed call (before strips, between kernels, after select)
+    std::vector<hipEvent_t> prof_events;
+    int32_t prof_capacity = 0;
+    int32_t prof_used = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            return;
+        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (ok && prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+void free_plan(ca_ctx *ctx, Plan *pl)
+{
+    if (pl->mem) {
+        (void)hipDeviceSynchronize();  // the plan may still be in use by queued work
+        (void)hipFree(pl->mem);
+        ctx->used -= pl->bytes;
+    }
+    delete pl;
+}
+
+int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p)
+{
+    if (p.n_hstrips < 0 || p.n_vstrips < 0 || p.n_hstrips > CA_MAX_STRIPS
+        || p.n_vstrips > CA_MAX_STRIPS || p.n_hstrips + p.n_vstrips < 1)
+        return CA_E_INVAL;
+    if (p.ransac_attempts < 1 || p.ransac_attempts > CA_MAX_ATTEMPTS)
+        return CA_E_INVAL;
+    if (p.refine_iters < 0 || p.refine_iters > 64 || (p.sampler != 0 && p.sampler != 1))
+        return CA_E_INVAL;
+    if (!(p.t_g > 0) || !(p.t_theta_deg > 0) || !(p.t_iota > 0) || !(p.t_ri >= 0)
+        || !std::isfinite(p.alpha) || !std::isfinite(p.t_ps) || !std::isfinite(p.t_cs)
+        || !std::isfinite(p.r_min) || !std::isfinite(p.r_max) || !std::isfinite(p.d_max)
+        || !std::isfinite(p.t_ri) || p.t_px < 0)
+        return CA_E_INVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        const ca_frame_desc &d = dims[i];
+        if (d.width < 16 || d.height < 16 || d.width > CA_MAX_EXTENT || d.height > CA_MAX_EXTENT)
+            return CA_E_INVAL;
+        if (d.byte_offset < 0 || (int64_t)d.row_stride < 3 * (int64_t)d.width)
+            return CA_E_INVAL;
+        if (d.pixel_stride != 3)
+            return CA_E_UNSUPPORTED;
+    }
+    return CA_OK;
+}
+
+int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out)
+{
+    Plan *pl = new (std::nothrow) Plan();
+    if (!pl)
+        return CA_E_NOMEM;
+    pl->dims.assign(dims, dims + n);
+    pl->n_frames = n;
+    pl->n_h = p.n_hstrips;
+    pl->n_v = p.n_vstrips;
+    pl->attempts = p.ransac_attempts;
+    pl->alpha = p.alpha;
+    pl->t_g = p.t_g;
+    pl->t_theta = p.t_theta_deg;
+    pl->t_iota = p.t_iota;
+    pl->P = 2 * (p.n_hstrips + p.n_vstrips);
+    pl->groups = (p.ransac_attempts + ca::kBlock - 1) / ca::kBlock;
+
+    // host images of the tables
+    const int S = p.n_hstrips + p.n_vstrips;
+    std::vector<Shape> shapes;
+    std::vector<int32_t> strips;
+    std::vector<FrameDev> fd((size_t)n);
+    int32_t longest = 0;
+    pl->rows_aligned = true;
+    for (int32_t i = 0; i < n; ++i) {
+        const ca_frame_desc &d = dims[i];
+        size_t k = 0;
+        while (k < shapes.size() && !(shapes[k].W == d.width && shapes[k].H == d.height))
+            ++k;
+        if (k == shapes.size()) {
+            shapes.push_back({d.width, d.height});
+            const size_t at = strips.size();
+            strips.resize(at + (size_t)S);
+            strip_positions(d.height, p.n_hstrips, p.alpha, strips.data() + at);
+            strip_positions(d.width, p.n_vstrips, p.alpha, strips.data() + at + p.n_hstrips);
+        }
+        fd[(size_t)i] = FrameDev{d.byte_offset, d.width, d.height, d.row_stride,
+                                 (int32_t)(k * (size_t)S), d.frame_uid};
+        longest = d.width > longest ? d.width : longest;
+        longest = d.height > longest ? d.height : longest;
+        if ((d.byte_offset % 16) != 0 || (d.row_stride % 16) != 0)
+            pl->rows_aligned = false;
+    }
+    std::vector<float> lut((size_t)CA_SG_CAPACITY + ca::kQtBins + ca::kLumaLevels);
+    int32_t sg_len = 0;
+    std::vector<float> st(ca::kQtBins), si(ca::kLumaLevels);
+    score_tables(p, lut.data(), &sg_len, st.data(), si.data());
+    std::memcpy(lut.data() + sg_len, st.data(), sizeof(float) * ca::kQtBins);
+    std::memcpy(lut.data() + sg_len + ca::kQtBins, si.data(), sizeof(float) * ca::kLumaLevels);
+    lut.resize((size_t)sg_len + ca::kQtBins + ca::kLumaLevels);
+    pl->sg_len = sg_len;
+    pl->line_pitch = (int32_t)align_up((size_t)longest, 16);
+    pl->lds = ca::strip_lds_bytes(sg_len, pl->line_pitch);
+    if (pl->lds > ctx->max_lds) {
+        delete pl;
+        return CA_E_UNSUPPORTED;
+    }
+
+    // one device allocation: frames | strips | lut | candidates | records
+    const size_t o_fd = 0;
+    const size_t o_strips = align_up(o_fd + sizeof(FrameDev) * (size_t)n, 256);
+    const size_t o_lut = align_up(o_strips + sizeof(int32_t) * strips.size(), 256);
+    const size_t o_cand = align_up(o_lut + sizeof(float) * lut.size(), 256);
+    const size_t o_rec = align_up(o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
+    const size_t total = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
+
+    // evict least recently used plans until this one fits the budget
+    while (ctx->used + total > ctx->budget && !ctx->plans.empty()) {
+        size_t lru = 0;
+        for (size_t k = 1; k < ctx->plans.size(); ++k)
+            if (ctx->plans[k]->last_use < ctx->plans[lru]->last_use)
+                lru = k;
+        free_plan(ctx, ctx->plans[lru]);
+        ctx->plans.erase(ctx->plans.begin() + (long)lru);
+    }
+    if (ctx->used + total > ctx->budget) {
+        delete pl;
+        return CA_E_NOMEM;
+    }
+    if (hipMalloc(&pl->mem, total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete pl;
+        return CA_E_NOMEM;
+    }
+    pl->bytes = total;
+    ctx->used += total;
+    uint8_t *base = static_cast<uint8_t *>(pl->mem);
+    pl->fd = reinterpret_cast<FrameDev *>(base + o_fd);
+    pl->strips = reinterpret_cast<int32_t *>(base + o_strips);
+    pl->lut = reinterpret_cast<float *>(base + o_lut);
+    pl->cand = reinterpret_cast<ca_point *>(base + o_cand);
+    pl->rec = reinterpret_cast<Record *>(base + o_rec);
+    // plans are built once per batch shape; a blocking upload keeps them simple
+    bool ok = hipMemcpy(pl->fd, fd.data(), sizeof(FrameDev) * (size_t)n, hipMemcpyHostToDevice)
+                  == hipSuccess
+              && hipMemcpy(pl->strips, strips.data(), sizeof(int32_t) * strips.size(),
+                           hipMemcpyHostToDevice)
+                     == hipSuccess
+              && hipMemcpy(pl->lut, lut.data(), sizeof(float) * lut.size(), hipMemcpyHostToDevice)
+                     == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_plan(ctx, pl);
+        return CA_E_DEVICE;
+    }
+    ctx->plans.push_back(pl);
+    *out = pl;
+    return CA_OK;
+}
+
+int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+        const ca_params *params, ca_point *points_out, ca_attempt *attempts_out, ca_result *out,
+        void *stream)
+{
+    if (!ctx || n < 0)
+        return CA_E_INVAL;
+    if (n == 0)
+        return CA_OK;
+    if (!frames || !dims || !out)
+        return CA_E_INVAL;
+    ca_params p;
+    if (params)
+        p = *params;
+    else
+        ca_default_params(&p);
+    int rc = validate(dims, n, p);
+    if (rc != CA_OK)
+        return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+
+    Plan *pl = nullptr;
+    for (Plan *c : ctx->plans)
+        if (same_key(*c, dims, n, p)) {
+            pl = c;
+            break;
+        }
+    if (!pl) {
+        rc = build_plan(ctx, dims, n, p, &pl);
+        if (rc != CA_OK)
+            return rc;
+    }
+    pl->last_use = ++ctx->tick;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    ca::StripArgs sa;
+    sa.frames = frames;
+    sa.fd = pl->fd;
+    sa.strips = pl->strips;
+    sa.lut = pl->lut;
+    sa.cand = points_out ? points_out : pl->cand;
+    sa.sg_len = pl->sg_len;
+    sa.n_h = p.n_hstrips;
+    sa.n_v = p.n_vstrips;
+    sa.n_items = n * (p.n_hstrips + p.n_vstrips);
+    sa.per_xcd = (sa.n_items + 7) / 8;
+    sa.line_pitch = pl->line_pitch;
+    sa.aligned = (pl->rows_aligned && (reinterpret_cast<uintptr_t>(frames) % 16) == 0) ? 1 : 0;
+
+    ca::RansacArgs ra;
+    ra.fd = pl->fd;
+    ra.cand = sa.cand;
+    ra.rec = pl->rec;
+    ra.dbg = attempts_out;
+    ra.seed = p.seed;
+    ra.t_ri = p.t_ri;
+    ra.r_min = p.r_min;
+    ra.r_max = p.r_max;
+    ra.d_max = p.d_max;
+    ra.t_ps = (float)p.t_ps;
+    ra.t_px = p.t_px;
+    ra.P = pl->P;
+    ra.attempts = p.ransac_attempts;
+    ra.refine = p.refine_iters;
+    ra.sampler = p.sampler;
+    ra.groups = pl->groups;
+
+    ca::SelectArgs se;
+    se.rec = pl->rec;
+    se.out = out;
+    se.threshold = p.t_cs * 16777216.0 * (double)pl->P;
+    se.P = pl->P;
+    se.groups = pl->groups;
+    se.n_frames = n;
+
+    hipEvent_t *ev = nullptr;
+    if (ctx->prof_used < ctx->prof_capacity)
+        ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
+    if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
+        || ca::launch_strips(sa, pl->lds, s) != hipSuccess
+        || (ev && hipEventRecord(ev[1], s) != hipSuccess)
+        || ca::launch_ransac(ra, n, s) != hipSuccess
+        || (ev && hipEventRecord(ev[2], s) != hipSuccess)
+        || ca::launch_select(se, s) != hipSuccess
+        || (ev && hipEventRecord(ev[3], s) != hipSuccess))
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ca_default_params(ca_params *p)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    // Appendix A, Table A1; three refinements (Section 2.2.5)
+    p->n_hstrips = 16;
+    p->n_vstrips = 16;
+    p->alpha = 8.0;
+    p->t_g = 20.0;
+    p->t_theta_deg = 30.0;
+    p->t_iota = 25.0;
+    p->t_ps = 0.03;
+    p->t_cs = 0.06;
+    p->t_px = 3;
+    p->refine_iters = 3;
+    p->t_ri = 3.0;
+    p->r_min = 0.1;
+    p->r_max = 0.8;
+    p->d_max = 0.2;
+    p->ransac_attempts = 256;
+    p->sampler = 0;
+    p->seed = 0;
+}
+
+int ca_create(ca_ctx **out, int device, size_t budget)
+{
+    if (!out)
+        return CA_E_INVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) {
+        (void)hipGetLastError();
+        return CA_E_DEVICE;
+    }
+    if (device < 0 || device >= count)
+        return CA_E_INVAL;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device)
+        != hipSuccess)
+        return CA_E_DEVICE;
+    ca_ctx *c = new (std::nothrow) ca_ctx();
+    if (!c)
+        return CA_E_NOMEM;
+    c->device = device;
+    c->budget = budget ? budget : ((size_t)1 << 30);
+    c->max_lds = (size_t)lds;
+    *out = c;
+    return CA_OK;
+}
+
+static void release_profile(ca_ctx *ctx)
+{
+    for (hipEvent_t e : ctx->prof_events)
+        (void)hipEventDestroy(e);
+    ctx->prof_events.clear();
+    ctx->prof_capacity = 0;
+    ctx->prof_used = 0;
+}
+
+void ca_destroy(ca_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    {
+        DeviceGuard guard(ctx->device);
+        (void)hipDeviceSynchronize();
+        release_profile(ctx);
+        for (Plan *p : ctx->plans)
+            free_plan(ctx, p);
+    }
+    delete ctx;
+}
+
+int ca_profile_begin(ca_ctx *ctx, int32_t max_calls)
+{
+    if (!ctx || max_calls < 1)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    (void)hipDeviceSynchronize();
+    release_profile(ctx);
+    try {
+        ctx->prof_events.assign(4 * (size_t)max_calls, nullptr);
+    } catch (...) {
+        return CA_E_NOMEM;
+    }
+    for (hipEvent_t &e : ctx->prof_events)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            release_profile(ctx);
+            return CA_E_DEVICE;
+        }
+    ctx->prof_capacity = max_calls;
+    ctx->prof_used = 0;
+    return CA_OK;
+}
+
+int ca_profile_end(ca_ctx *ctx, ca_kernel_times *out)
+{
+    if (!ctx || !out)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    std::memset(out, 0, sizeof(*out));
+    int rc = CA_OK;
+    for (int32_t c = 0; c < ctx->prof_used; ++c) {
+        hipEvent_t *ev = &ctx->prof_events[4 * (size_t)c];
+        if (hipEventSynchronize(ev[3]) != hipSuccess) {
+            rc = CA_E_DEVICE;
+            break;
+        }
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) {
+                rc = CA_E_DEVICE;
+                break;
+            }
+            out->total_ms[k] += ms;
+            out->launches[k] += 1;
+        }
+    }
+    release_profile(ctx);
+    return rc;
+}
+
+int ca_estimate_area(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+                     const ca_params *params, ca_result *out, void *stream)
+{
+    try {
+        return run(ctx, frames, dims, n, params, nullptr, nullptr, out, stream);
+    } catch (...) {
+        return CA_E_NOMEM;
+    }
+}
+
+int ca_debug_candidates(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+                        const ca_params *params, ca_point *points, ca_result *out, void *stream)
+{
+    if (n > 0 && !points)
+        return CA_E_INVAL;
+    try {
+        return run(ctx, frames, dims, n, params, points, nullptr, out, stream);
+    } catch (...) {
+        return CA_E_NOMEM;
+    }
+}
+
+int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+                      const ca_params *params, ca_attempt *attempts, ca_result *out, void *stream)
+{
+    if (n > 0 && !attempts)
+        return CA_E_INVAL;
+    try {
+        return run(ctx, frames, dims, n, params, nullptr, attempts, out, stream);
+    } catch (...) {
+        return CA_E_NOMEM;
+    }
+}
+
+int ca_check_args(const ca_frame_desc *dims, int32_t n, const ca_params *params)
+{
+    if (n < 0 || (n > 0 && !dims))
+        return CA_E_INVAL;
+    ca_params p;
+    if (params)
+        p = *params;
+    else
+        ca_default_params(&p);
+    return validate(dims, n, p);
+}
+
+int ca_strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos)
+{
+    if (!pos && n > 0)
+        return CA_E_INVAL;
+    return strip_positions(extent, n, alpha, pos);
+}
+
+int ca_score_tables(const ca_params *p, float *sg, int32_t *sg_len, float *st, float *si)
+{
+    if (!sg || !sg_len || !st || !si)
+        return CA_E_INVAL;
+    ca_params q;
+    if (p)
+        q = *p;
+    else
+        ca_default_params(&q);
+    if (!(q.t_g > 0) || !(q.t_theta_deg > 0) || !(q.t_iota > 0))
+        return CA_E_INVAL;
+    return score_tables(q, sg, sg_len, st, si);
+}
+
+const char *ca_error_string(int code)
+{
+    switch (code) {
+    case CA_OK:
+        return "ok";
+    case CA_E_INVAL:
+        return "invalid argument";
+    case CA_E_UNSUPPORTED:
+        return "unsupported frame layout or parameter combination";
+    case CA_E_NOMEM:
+        return "workspace budget exceeded or out of memory";
+    case CA_E_DEVICE:
+        return "HIP runtime error";
+    default:
+        return "unknown error";
+    }
+}
+
+const char *ca_version(void) { return "contentarea-gfx950 0.1.0"; }
+
+}  // extern "C"

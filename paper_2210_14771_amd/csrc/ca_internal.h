@@ -1,0 +1,80 @@
+// Internal interface between the host core (ca_api.cpp) and the gfx950
+// kernels (ca_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "contentarea.h"
+
+namespace ca {
+
+constexpr int kBlock = 256;      // threads per workgroup of every kernel
+constexpr int kHalfThreads = 128; // threads per half strip
+constexpr int kChunk = 16;       // most pixels one thread scores per pass
+constexpr int kQtBins = 2049;    // pseudo-angle bins, 0 .. 2048
+constexpr int kLumaLevels = 256;
+
+// One frame as the kernels see it (32 bytes).
+struct FrameDev {
+    int64_t offset;   // first byte relative to the frames base
+    int32_t W, H;
+    int32_t rs;       // row stride in bytes
+    int32_t table;    // index of the frame's first strip position in the strip table
+    uint64_t uid;     // RNG counter word
+};
+
+// Best attempt of one (frame, attempt group).
+struct Record {
+    uint64_t key;     // (qsum << 16) | (0xFFFF - attempt); 0 = nothing kept
+    double cx, cy, r2;
+    int32_t inliers;
+    int32_t n_points;
+    int32_t pad[2];
+};
+
+struct StripArgs {
+    const uint8_t *frames;
+    const FrameDev *fd;
+    const int32_t *strips;  // per distinct frame shape: n_h rows then n_v columns
+    const float *lut;       // SG[sg_len] | ST[2049] | SI[256]
+    ca_point *cand;         // [n_frames][P]
+    int32_t sg_len;
+    int32_t n_h, n_v;
+    int32_t n_items;        // n_frames * (n_h + n_v)
+    int32_t per_xcd;        // items per XCD slice (grid = 8 * per_xcd)
+    int32_t line_pitch;     // bytes per LDS tile row (>= longest line, multiple of 16)
+    int32_t aligned;        // every frame row starts 16-byte aligned
+};
+
+struct RansacArgs {
+    const FrameDev *fd;
+    const ca_point *cand;
+    Record *rec;            // [n_frames][groups]
+    ca_attempt *dbg;        // optional per-attempt records
+    uint64_t seed;
+    double t_ri, r_min, r_max, d_max;
+    float t_ps;
+    int32_t t_px;
+    int32_t P;
+    int32_t attempts;
+    int32_t refine;
+    int32_t sampler;
+    int32_t groups;         // attempt groups per frame
+};
+
+struct SelectArgs {
+    const Record *rec;
+    ca_result *out;
+    double threshold;       // t_cs * 2^24 * P
+    int32_t P;
+    int32_t groups;
+    int32_t n_frames;
+};
+
+size_t strip_lds_bytes(int sg_len, int line_pitch);
+hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_ransac(const RansacArgs &a, int n_frames, hipStream_t s);
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+
+}  // namespace ca

@@ -1,0 +1,655 @@
+// gfx950 kernels of the content-area estimator (arXiv 2210.14771, Section 2.2).
+//
+// k_strips  one workgroup per (frame, strip): stage the strip's three lines
+//           as 8-bit luma in LDS, score every pixel of both half strips
+//           (Sobel, angle to the image centre, preceding maximum; Eqs. 2-3)
+//           and keep the best pixel of each half (Section 2.2.5).  The
+//           preceding-maximum scan and the argmax -- the two operations the
+//           paper singles out as needing block-wide cooperation (Section
+//           2.2.6) -- are wave64 shuffle scans/reductions joined through LDS.
+// k_ransac  one thread per RANSAC attempt, attempts split over workgroups of
+//           256; kept points are compacted into LDS and read by broadcast.
+// k_select  merges the per-workgroup best attempts of each frame.
+//
+// Numeric contract (shared with the CPU oracle by definition, not by code):
+// integer luma and Sobel, exact integer quantisers for |g| and the angle,
+// float32 table lookups and products in a fixed order, float64 circle
+// arithmetic without contraction (build with -ffp-contract=off), integer
+// inlier moments (summed here in float64, exact below 2^53).
+#include "ca_internal.h"
+
+namespace ca {
+namespace {
+
+constexpr uint32_t kWave = 64;
+
+__device__ __forceinline__ uint32_t luma_of(uint32_t r, uint32_t g, uint32_t b)
+{
+    return (77u * r + 150u * g + 29u * b + 128u) >> 8;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        uint32_t t = (uint32_t)__shfl_up((int)v, d, kWave);
+        if (lane >= d)
+            v = v > t ? v : t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        uint64_t t = __shfl_xor(v, d, kWave);
+        v = v > t ? v : t;
+    }
+    return v;
+}
+
+// s_g * s_theta of one pixel from its Sobel gradient (Eq. 2, quantised).
+__device__ __forceinline__ float grad_angle_score(int gx, int gy, int x, int y, int W, int H,
+                                                  const float *sg, int sg_last, const float *st)
+{
+    const int m2 = gx * gx + gy * gy;
+    if (m2 == 0)
+        return 0.0f;  // SG[0] = 0
+    // qg = floor(8 |g|) = isqrt(64 m2): float estimate, then exact correction
+    const uint32_t v = (uint32_t)m2 * 64u;
+    uint32_t q = (uint32_t)__builtin_amdgcn_sqrtf((float)v);
+    if (q * q > v)
+        --q;
+    if ((q + 1) * (q + 1) <= v)
+        ++q;
+    const int qg = (int)q < sg_last ? (int)q : sg_last;
+    // doubled vector from the pixel to the image centre
+    const int c2x = W - 1 - 2 * x;
+    const int c2y = H - 1 - 2 * y;
+    const int dt = gx * c2x + gy * c2y;
+    const int cr = gx * c2y - gy * c2x;
+    const uint32_t acr = (uint32_t)(cr < 0 ? -cr : cr);
+    const uint32_t adt = (uint32_t)(dt < 0 ? -dt : dt);
+    const uint32_t den = acr + adt;
+    int qt = 0;
+    if (den != 0) {
+        // f = floor(1024 acr / den): reciprocal estimate within one of the
+        // true quotient (relative error ~2^-21 on a value <= 1024), then an
+        // exact integer correction
+        const uint64_t num = (uint64_t)acr << 10;
+        uint32_t f = (uint32_t)((float)acr * 1024.0f * __builtin_amdgcn_rcpf((float)den));
+        uint64_t fd = (uint64_t)f * den;
+        if (fd > num) {
+            --f;
+            fd -= den;
+        } else if (fd + den <= num) {
+            ++f;
+            fd += den;
+        }
+        qt = dt >= 0 ? (int)f : 2048 - (int)(f + (fd != num ? 1u : 0u));
+    }
+    return sg[qg] * st[qt];
+}
+
+// ---------------------------------------------------------------------------
+// k_strips
+// ---------------------------------------------------------------------------
+
+// Stage luma of the three lines of a horizontal strip centred on `row`.
+__device__ void load_hstrip(const uint8_t *frame, int W, int rs, int row, uint8_t *tile, int LP,
+                            bool aligned)
+{
+    const int tid = threadIdx.x;
+    int x_done = 0;
+    if (aligned) {
+        // 16 pixels (48 bytes, three 16-byte loads) per work unit
+        const int groups = W >> 4;
+        for (int t = tid; t < 3 * groups; t += kBlock) {
+            const int a = t / groups;
+            const int gi = t - a * groups;
+            const uint4 *src =
+                reinterpret_cast<const uint4 *>(frame + (int64_t)(row - 1 + a) * rs + gi * 48);
+            const uint4 q0 = src[0], q1 = src[1], q2 = src[2];
+            const uint32_t w[12] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y,
+                                    q1.z, q1.w, q2.x, q2.y, q2.z, q2.w};
+            uint32_t out[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                const int b0 = 3 * p;
+                const uint32_t r = (w[b0 >> 2] >> (8 * (b0 & 3))) & 0xFFu;
+                const uint32_t g = (w[(b0 + 1) >> 2] >> (8 * ((b0 + 1) & 3))) & 0xFFu;
+                const uint32_t b = (w[(b0 + 2) >> 2] >> (8 * ((b0 + 2) & 3))) & 0xFFu;
+                out[p >> 2] |= luma_of(r, g, b) << (8 * (p & 3));
+            }
+            *reinterpret_cast<uint4 *>(tile + a * LP + gi * 16) =
+                make_uint4(out[0], out[1], out[2], out[3]);
+        }
+        x_done = groups << 4;
+    }
+    const int rest = W - x_done;
+    for (int t = tid; t < 3 * rest; t += kBlock) {
+        const int a = t / rest;
+        const int x = x_done + (t - a * rest);
+        const uint8_t *px = frame + (int64_t)(row - 1 + a) * rs + 3 * x;
+        tile[a * LP + x] = (uint8_t)luma_of(px[0], px[1], px[2]);
+    }
+}
+
+// Stage luma of the three columns of a vertical strip centred on `col`.
+__device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col, uint8_t *tile,
+                            int LP)
+{
+    const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
+    const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
+    for (int y = threadIdx.x; y < H; y += kBlock) {
+        const uint8_t *p = frame + (int64_t)y * rs + 3 * (col - 1);
+        const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+        const uintptr_t al = addr & ~(uintptr_t)3;
+        uint32_t b03, b47, b8;
+        if (al >= fstart && al + 12 <= fend) {
+            // the 9 bytes lie inside 3 aligned dwords; extract with v_alignbyte
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(al);
+            const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+            const uint32_t sh = (uint32_t)(addr - al);
+            b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+            b8 = (w2 >> (8 * sh)) & 0xFFu;
+        } else {
+            b03 = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16)
+                  | ((uint32_t)p[3] << 24);
+            b47 = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16)
+                  | ((uint32_t)p[7] << 24);
+            b8 = p[8];
+        }
+        tile[0 * LP + y] = (uint8_t)luma_of(b03 & 0xFFu, (b03 >> 8) & 0xFFu, (b03 >> 16) & 0xFFu);
+        tile[1 * LP + y] = (uint8_t)luma_of(b03 >> 24, b47 & 0xFFu, (b47 >> 8) & 0xFFu);
+        tile[2 * LP + y] = (uint8_t)luma_of((b47 >> 16) & 0xFFu, b47 >> 24, b8);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    float *s_sg = reinterpret_cast<float *>(smem);
+    float *s_st = s_sg + a.sg_len;
+    float *s_si = s_st + kQtBins;
+    uint8_t *tile = reinterpret_cast<uint8_t *>(s_si + kLumaLevels);
+    tile = reinterpret_cast<uint8_t *>((reinterpret_cast<uintptr_t>(tile) + 15) & ~(uintptr_t)15);
+    __shared__ uint32_t s_scan[4];
+    __shared__ uint64_t s_best[4];
+
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+    // so workgroup b runs on XCD b % 8; give each XCD a contiguous slice of
+    // (frame, strip) items so one frame's strips share that XCD's L2.
+    const int b = blockIdx.x;
+    const int item = (b & 7) * a.per_xcd + (b >> 3);
+    if (item >= a.n_items)
+        return;
+
+    const int tid = threadIdx.x;
+    const int lut_n = a.sg_len + kQtBins + kLumaLevels;
+    for (int i = tid; i < lut_n; i += kBlock)
+        s_sg[i] = a.lut[i];
+
+    const int S = a.n_h + a.n_v;
+    const int f = item / S;
+    const int s = item - f * S;
+    const FrameDev d = a.fd[f];
+    const uint8_t *frame = a.frames + d.offset;
+    const bool horizontal = s < a.n_h;
+    const int pos = a.strips[d.table + s];
+    const int L = horizontal ? d.W : d.H;
+    const int LP = a.line_pitch;
+    if (horizontal)
+        load_hstrip(frame, d.W, d.rs, pos, tile, LP, a.aligned != 0);
+    else
+        load_vstrip(frame, d.W, d.H, d.rs, pos, tile, LP);
+    __syncthreads();
+
+    const int half = tid >> 7;
+    const int lt = tid & (kHalfThreads - 1);
+    const int wv = tid >> 6;
+    const uint32_t lane = tid & (kWave - 1);
+    const int Lh = half == 0 ? (L >> 1) : L - (L >> 1);
+    const int Lmax = L - (L >> 1);
+    int chunk = (Lmax + kHalfThreads - 1) / kHalfThreads;
+    chunk = chunk < kChunk ? chunk : kChunk;
+    const int span = kHalfThreads * chunk;
+    const int n_pass = (Lmax + span - 1) / span;
+    const int sg_last = a.sg_len - 1;
+    const uint8_t *t0 = tile, *t1 = tile + LP, *t2 = tile + 2 * LP;
+
+    uint32_t carry = 0;
+    uint64_t best = 0;
+    for (int pass = 0; pass < n_pass; ++pass) {
+        const int k0 = pass * span + lt * chunk;
+        float part[kChunk];
+        uint32_t lum[kChunk];
+        uint32_t tmax = 0;
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            part[j] = 0.0f;
+            lum[j] = 0;
+            const int k = k0 + j;
+            if (j < chunk && k < Lh) {
+                const int i = half == 0 ? k : L - 1 - k;
+                const int im = i > 0 ? i - 1 : 0;
+                const int ip = i < L - 1 ? i + 1 : L - 1;
+                const int along = ((int)t0[ip] + 2 * (int)t1[ip] + (int)t2[ip])
+                                  - ((int)t0[im] + 2 * (int)t1[im] + (int)t2[im]);
+                const int across = ((int)t2[im] + 2 * (int)t2[i] + (int)t2[ip])
+                                   - ((int)t0[im] + 2 * (int)t0[i] + (int)t0[ip]);
+                const uint32_t y1 = t1[i];
+                part[j] = horizontal
+                              ? grad_angle_score(along, across, i, pos, d.W, d.H, s_sg, sg_last, s_st)
+                              : grad_angle_score(across, along, pos, i, d.W, d.H, s_sg, sg_last, s_st);
+                lum[j] = y1;
+                tmax = tmax > y1 ? tmax : y1;
+            }
+        }
+        // exclusive max-scan of the chunk maxima over the 128 threads of this half
+        const uint32_t incl = wave_incl_max(tmax);
+        uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, kWave);
+        if (lane == 0)
+            excl = 0;
+        if (lane == kWave - 1)
+            s_scan[wv] = incl;
+        __syncthreads();
+        const uint32_t w0 = s_scan[2 * half], w1 = s_scan[2 * half + 1];
+        if (wv & 1)
+            excl = excl > w0 ? excl : w0;
+        uint32_t run = carry > excl ? carry : excl;
+        const uint32_t tot = w0 > w1 ? w0 : w1;
+        carry = carry > tot ? carry : tot;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            const int k = k0 + j;
+            if (j < chunk && k < Lh) {
+                const float sc = part[j] * s_si[run];
+                const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
+                                     | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+                best = best > key ? best : key;
+                run = run > lum[j] ? run : lum[j];
+            }
+        }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0)
+        s_best[wv] = best;
+    __syncthreads();
+    if (lt == 0) {
+        const uint64_t b0 = s_best[2 * half], b1 = s_best[2 * half + 1];
+        const uint64_t bb = b0 > b1 ? b0 : b1;
+        const int k = (int)(0xFFFFFFFFu - (uint32_t)bb);
+        const int i = half == 0 ? k : L - 1 - k;
+        ca_point pt;
+        pt.x = (int16_t)(horizontal ? i : pos);
+        pt.y = (int16_t)(horizontal ? pos : i);
+        pt.score = __uint_as_float((uint32_t)(bb >> 32));
+        a.cand[(int64_t)f * (2 * S) + 2 * s + half] = pt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_ransac
+// ---------------------------------------------------------------------------
+
+struct Lds {
+    double2 uv[kBlock];     // shifted coordinates u, v
+    double2 m1[kBlock];     // u^2, u v
+    double2 m2[kBlock];     // v^2, z = u^2 + v^2
+    double2 m3[kBlock];     // u z, v z
+    double q[kBlock];       // floor(score * 2^24)
+    int iu[kBlock], iv[kBlock];
+    int wcount[4];
+    uint64_t wbest[4];
+};
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    // Salmon et al., SC'11: Philox4x64 with 10 rounds
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__device__ __forceinline__ int below(uint64_t u, int k)
+{
+    return (int)(((u >> 32) * (uint64_t)(uint32_t)k) >> 32);
+}
+
+__device__ bool pick_triple(const RansacArgs &a, uint64_t uid, int att, int n, int t[3])
+{
+    if (a.sampler == 0) {
+        uint64_t c[4] = {(uint64_t)(uint32_t)att, uid, 0, 0};
+        philox4x64_10(c, a.seed, 0);
+        const int i0 = below(c[0], n);
+        int i1 = below(c[1], n - 1);
+        i1 += i1 >= i0;
+        const int lo = i0 < i1 ? i0 : i1, hi = i0 < i1 ? i1 : i0;
+        int i2 = below(c[2], n - 2);
+        i2 += i2 >= lo;
+        i2 += i2 >= hi;
+        t[0] = i0;
+        t[1] = i1;
+        t[2] = i2;
+        return true;
+    }
+    // lexicographic enumeration: the att-th triple i < j < k
+    int64_t r = att;
+    for (int i = 0; i < n - 2; ++i) {
+        const int64_t cnt = (int64_t)(n - 1 - i) * (n - 2 - i) / 2;
+        if (r >= cnt) {
+            r -= cnt;
+            continue;
+        }
+        for (int j = i + 1; j < n - 1; ++j) {
+            const int64_t cj = n - 1 - j;
+            if (r >= cj) {
+                r -= cj;
+                continue;
+            }
+            t[0] = i;
+            t[1] = j;
+            t[2] = j + 1 + (int)r;
+            return true;
+        }
+    }
+    return false;
+}
+
+struct Band {
+    double cx, cy, lo2, hi2;
+};
+
+__device__ __forceinline__ Band make_band(double cx, double cy, double r2, double t)
+{
+    Band b;
+    const double r = sqrt(r2);
+    const double hi = r + t;
+    b.cx = cx;
+    b.cy = cy;
+    b.hi2 = hi * hi;
+    if (r > t) {
+        const double lo = r - t;
+        b.lo2 = lo * lo;
+    } else {
+        b.lo2 = -1.0;
+    }
+    return b;
+}
+
+// One inlier pass + Coope least-squares refit (Section 2.2.5).
+__device__ bool refit(const Lds &L, int n, const Band &b, double &cx, double &cy, double &r2)
+{
+    double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0;
+    for (int i = 0; i < n; ++i) {
+        const double2 p = L.uv[i];
+        const double du = p.x - b.cx;
+        const double dv = p.y - b.cy;
+        const double d2 = du * du + dv * dv;
+        const double w = (b.lo2 <= d2 && d2 <= b.hi2) ? 1.0 : 0.0;
+        const double2 m1 = L.m1[i], m2 = L.m2[i], m3 = L.m3[i];
+        S0 += w;
+        S1 = fma(w, p.x, S1);
+        S2 = fma(w, p.y, S2);
+        S3 = fma(w, m1.x, S3);
+        S4 = fma(w, m1.y, S4);
+        S5 = fma(w, m2.x, S5);
+        S6 = fma(w, m2.y, S6);
+        S7 = fma(w, m3.x, S7);
+        S8 = fma(w, m3.y, S8);
+    }
+    const int64_t m = (int64_t)S0;
+    if (m < 3)
+        return false;
+    const int64_t Su = (int64_t)S1, Sv = (int64_t)S2, Suu = (int64_t)S3, Suv = (int64_t)S4;
+    const int64_t Svv = (int64_t)S5, Sz = (int64_t)S6, Suz = (int64_t)S7, Svz = (int64_t)S8;
+    const int64_t Cuu = m * Suu - Su * Su;
+    const int64_t Cuv = m * Suv - Su * Sv;
+    const int64_t Cvv = m * Svv - Sv * Sv;
+    const int64_t Cuz = m * Suz - Su * Sz;
+    const int64_t Cvz = m * Svz - Sv * Sz;
+    const double det = (double)Cuu * (double)Cvv - (double)Cuv * (double)Cuv;
+    if (det == 0.0)
+        return false;
+    const double A = ((double)Cuz * (double)Cvv - (double)Cvz * (double)Cuv) / det;
+    const double B = ((double)Cvz * (double)Cuu - (double)Cuz * (double)Cuv) / det;
+    cx = A / 2.0;
+    cy = B / 2.0;
+    const double mu = (double)Su / (double)m;
+    const double mv = (double)Sv / (double)m;
+    const double var = (double)(Cuu + Cvv) / ((double)m * (double)m);
+    r2 = (var + (mu - cx) * (mu - cx)) + (mv - cy) * (mv - cy);
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
+{
+    __shared__ Lds L;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid >> 6;
+    const int f = blockIdx.y;
+    const int g = blockIdx.x;
+    const FrameDev d = a.fd[f];
+    const int ox = d.W / 2, oy = d.H / 2;
+
+    // filter (Section 2.2.5) and stable compaction in canonical order
+    bool keep = false;
+    int x = 0, y = 0;
+    float sc = 0.0f;
+    if (tid < a.P) {
+        const ca_point pt = a.cand[(int64_t)f * a.P + tid];
+        x = pt.x;
+        y = pt.y;
+        sc = pt.score;
+        int ed = x < y ? x : y;
+        ed = ed < d.W - 1 - x ? ed : d.W - 1 - x;
+        ed = ed < d.H - 1 - y ? ed : d.H - 1 - y;
+        keep = ed >= a.t_px && sc >= a.t_ps;
+    }
+    const uint64_t ball = __ballot(keep);
+    const int before = __popcll(ball & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        L.wcount[wv] = __popcll(ball);
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wv; ++w)
+        base += L.wcount[w];
+    const int n = L.wcount[0] + L.wcount[1] + L.wcount[2] + L.wcount[3];
+    if (keep) {
+        const int j = base + before;
+        const int u = x - ox, v = y - oy;
+        const double du = (double)u, dv = (double)v;
+        const double z = (double)((int64_t)u * u + (int64_t)v * v);
+        L.iu[j] = u;
+        L.iv[j] = v;
+        L.uv[j] = make_double2(du, dv);
+        L.m1[j] = make_double2((double)((int64_t)u * u), (double)((int64_t)u * v));
+        L.m2[j] = make_double2((double)((int64_t)v * v), z);
+        L.m3[j] = make_double2(du * z, dv * z);
+        L.q[j] = (double)(uint32_t)(sc * 16777216.0f);
+    }
+    __syncthreads();
+
+    const int att = g * kBlock + tid;
+    const bool active = att < a.attempts;
+    uint64_t key = 0;
+    ca_attempt rec = {};
+    if (n >= 3 && active) {
+        int t[3];
+        if (!pick_triple(a, d.uid, att, n, t)) {
+            rec.i0 = rec.i1 = rec.i2 = -1;
+            rec.fail_stage = -1;
+        } else {
+            rec.i0 = t[0];
+            rec.i1 = t[1];
+            rec.i2 = t[2];
+            const int64_t x0 = L.iu[t[0]], x1 = L.iu[t[1]], x2 = L.iu[t[2]];
+            const int64_t y0 = L.iv[t[0]], y1 = L.iv[t[1]], y2 = L.iv[t[2]];
+            const int64_t D = 2 * (x0 * (y1 - y2) + x1 * (y2 - y0) + x2 * (y0 - y1));
+            bool ok = D != 0;
+            double cx = 0, cy = 0, r2 = 0;
+            if (ok) {
+                const int64_t z0 = x0 * x0 + y0 * y0, z1 = x1 * x1 + y1 * y1, z2 = x2 * x2 + y2 * y2;
+                const int64_t Nx = z0 * (y1 - y2) + z1 * (y2 - y0) + z2 * (y0 - y1);
+                const int64_t Ny = z0 * (x2 - x1) + z1 * (x0 - x2) + z2 * (x1 - x0);
+                cx = (double)Nx / (double)D;
+                cy = (double)Ny / (double)D;
+                const double ddx = (double)x0 - cx, ddy = (double)y0 - cy;
+                r2 = ddx * ddx + ddy * ddy;
+                for (int k = 1; k <= a.refine; ++k) {
+                    const Band bd = make_band(cx, cy, r2, a.t_ri);
+                    if (!refit(L, n, bd, cx, cy, r2)) {
+                        rec.fail_stage = k;
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+            if (ok) {
+                const Band bd = make_band(cx, cy, r2, a.t_ri);
+                double cnt = 0, qs = 0;
+                for (int i = 0; i < n; ++i) {
+                    const double2 p = L.uv[i];
+                    const double du = p.x - bd.cx;
+                    const double dv = p.y - bd.cy;
+                    const double d2 = du * du + dv * dv;
+                    const double w = (bd.lo2 <= d2 && d2 <= bd.hi2) ? 1.0 : 0.0;
+                    cnt += w;
+                    qs = fma(w, L.q[i], qs);
+                }
+                const double acx = (double)ox + cx;
+                const double acy = (double)oy + cy;
+                const double r = sqrt(r2);
+                const double ex = acx - (double)(d.W - 1) / 2.0;
+                const double ey = acy - (double)(d.H - 1) / 2.0;
+                const double dlim = a.d_max * (double)d.W;
+                const bool kept = r >= a.r_min * (double)d.W && r <= a.r_max * (double)d.W
+                                  && ex * ex + ey * ey <= dlim * dlim;
+                rec.status = kept ? 2 : 1;
+                rec.inliers = (int32_t)cnt;
+                rec.qsum = (uint64_t)qs;
+                rec.cx = acx;
+                rec.cy = acy;
+                rec.r2 = r2;
+                if (kept)
+                    key = (rec.qsum << 16) | (uint64_t)(0xFFFFu - (uint32_t)att);
+            }
+        }
+    }
+    if (a.dbg && active)
+        a.dbg[(int64_t)f * a.attempts + att] = rec;
+
+    // best kept attempt of this workgroup: keys are unique per attempt
+    const uint64_t wmax = wave_max_u64(key);
+    if (lane == 0)
+        L.wbest[wv] = wmax;
+    __syncthreads();
+    uint64_t bmax = L.wbest[0];
+    for (int w = 1; w < 4; ++w)
+        bmax = bmax > L.wbest[w] ? bmax : L.wbest[w];
+    Record *out = a.rec + (int64_t)f * a.groups + g;
+    if (bmax == 0) {
+        if (tid == 0) {
+            Record r0 = {};
+            r0.n_points = n;
+            *out = r0;
+        }
+    } else if (key == bmax) {
+        Record r1 = {};
+        r1.key = key;
+        r1.cx = rec.cx;
+        r1.cy = rec.cy;
+        r1.r2 = rec.r2;
+        r1.inliers = rec.inliers;
+        r1.n_points = n;
+        *out = r1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_select
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_select(SelectArgs a)
+{
+    const int f = blockIdx.x * 64 + threadIdx.x;
+    if (f >= a.n_frames)
+        return;
+    const Record *r = a.rec + (int64_t)f * a.groups;
+    int best = 0;
+    for (int g = 1; g < a.groups; ++g)
+        if (r[g].key > r[best].key)
+            best = g;
+    const Record rb = r[best];
+    ca_result o = {};
+    o.n_points = rb.n_points;
+    if (rb.n_points < 3) {
+        o.reason = 1;
+    } else if (rb.key == 0) {
+        o.reason = 2;
+    } else {
+        const uint64_t qsum = rb.key >> 16;
+        o.cx = (float)rb.cx;
+        o.cy = (float)rb.cy;
+        o.r = (float)sqrt(rb.r2);
+        o.score = (float)((double)qsum / (16777216.0 * (double)a.P));
+        o.inliers = rb.inliers;
+        o.valid = (double)qsum >= a.threshold ? 1 : 0;
+        o.reason = o.valid ? 0 : 3;
+    }
+    a.out[f] = o;
+}
+
+}  // namespace
+
+size_t strip_lds_bytes(int sg_len, int line_pitch)
+{
+    return (size_t)(sg_len + kQtBins + kLumaLevels) * sizeof(float) + 16 + 3 * (size_t)line_pitch;
+}
+
+hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s)
+{
+    if (a.n_items <= 0)
+        return hipSuccess;
+    const dim3 grid(8 * a.per_xcd);
+    hipLaunchKernelGGL(k_strips, grid, dim3(kBlock), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ransac(const RansacArgs &a, int n_frames, hipStream_t s)
+{
+    if (n_frames <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_ransac, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t s)
+{
+    if (a.n_frames <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3((a.n_frames + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ca

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs -- candidates and per-attempt inliers bit-exact, circles
+within 1e-3 px -- at the small 640x480 size, the full 64 x 1080p batch,
+brute-force enumeration on tiny frames, and edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2210_14771_amd import api, synth
+
+from gpu_helpers import (assert_attempts_equal, assert_points_equal, assert_results_equal,
+                         gen_batch, run_gpu, run_oracle, say)
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(n_hstrips=16, n_vstrips=16, ransac_attempts=256)
+HD = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def est(torch_dev):
+    e = api.Estimator(0)
+    yield e
+    e.close()
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    return synth.make_batch(synth.SMALL_640x480)
+
+
+@pytest.fixture(scope="module")
+def hd_batch():
+    return gen_batch(synth.HD_1080p, 64)
+
+
+def _dev(torch, frames):
+    return torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+
+
+def _full_parity(torch, est, frames, kw, uids=None, attempts=True):
+    uids = list(range(len(frames))) if uids is None else uids
+    say(f"parity case: {frames.shape} {kw}")
+    fd = _dev(torch, frames)
+    g = run_gpu(est, fd, kw, uids, what=("pts", "att", "res") if attempts else ("pts", "res"))
+    r, p, a = run_oracle(frames, kw, uids, attempts=attempts)
+    assert_points_equal(g["pts"], p)
+    bits = None
+    if attempts:
+        bits = assert_attempts_equal(g["att"], a)
+        assert_results_equal(g["res_att"], r)
+    assert_results_equal(g["res"], r)
+    return g, r, bits
+
+
+def test_small_workload_parity(torch_dev, est, small_batch):
+    frames, specs = small_batch
+    g, r, bits = _full_parity(torch_dev, est, frames, SMALL)
+    say(f"circle values bit-identical: {bits[0]}/{bits[1]}")
+    assert bits[0] == bits[1]
+    assert all(int(x["valid"]) == 1 for x in r)
+
+
+def test_hd_workload_parity(torch_dev, est, hd_batch):
+    frames, specs = hd_batch
+    g, r, bits = _full_parity(torch_dev, est, frames, HD)
+    say(f"circle values bit-identical: {bits[0]}/{bits[1]}")
+    assert bits[0] == bits[1]
+
+
+def test_enumeration_equals_brute_force(torch_dev, est):
+    # tiny frames: every triple of the kept points is tried once
+    frames, _ = synth.make_batch(synth.SMALL_640x480, 6)
+    tiny = np.ascontiguousarray(frames[:, ::5, ::5])
+    kw = dict(n_hstrips=4, n_vstrips=3, ransac_attempts=4096, sampler=1)
+    g = run_gpu(est, _dev(torch_dev, tiny), kw, list(range(6)))
+    for i in range(6):
+        b = oracle.estimate_bruteforce(tiny[i], oracle.params(n_hstrips=4, n_vstrips=3,
+                                                              attempts=4096, sampler=1), i)
+        gr = g["res"][i]
+        assert gr["valid"] == b["valid"] and gr["inliers"] == b["inliers"]
+        assert gr["n_points"] == b["n_points"]
+        if b["best_attempt"] >= 0:
+            assert abs(float(gr["cx"]) - float(b["cx"])) <= 1e-3
+            assert abs(float(gr["r"]) - float(b["r"])) <= 1e-3
+    _full_parity(torch_dev, est, tiny, kw)
+
+
+@pytest.mark.parametrize("case", ["blank", "odd_unaligned", "padded_stride", "paper_literal",
+                                  "max_strips", "one_attempt", "no_refine", "tall",
+                                  "minimum_size", "enumerate_small"])
+def test_edge_cases(torch_dev, est, case):
+    torch = torch_dev
+    frames, _ = synth.make_batch(synth.SMALL_640x480, 3)
+    kw = dict(SMALL)
+    if case == "blank":
+        frames = np.stack([np.zeros((120, 160, 3), np.uint8), np.full((120, 160, 3), 255, np.uint8),
+                           np.full((120, 160, 3), 77, np.uint8)])
+    elif case == "odd_unaligned":
+        # odd width: rows are not 16-byte aligned, so the byte-wise load path runs
+        frames = np.ascontiguousarray(frames[:, 3:470, 5:606])
+    elif case == "paper_literal":
+        kw["n_vstrips"] = 0
+    elif case == "max_strips":
+        kw.update(n_hstrips=64, n_vstrips=64, ransac_attempts=4096)
+    elif case == "one_attempt":
+        kw["ransac_attempts"] = 1
+    elif case == "no_refine":
+        kw["refine_iters"] = 0
+    elif case == "tall":
+        frames = np.ascontiguousarray(frames.transpose(0, 2, 1, 3))
+    elif case == "minimum_size":
+        frames = np.ascontiguousarray(frames[:, 200:216, 300:316])
+    elif case == "enumerate_small":
+        kw.update(sampler=1, ransac_attempts=300)
+    if case == "padded_stride":
+        # rows 7 bytes longer than the pixels, frames at unaligned offsets
+        B, H, W, _ = frames.shape
+        rs = 3 * W + 7
+        buf = np.zeros(B * H * rs + 5, np.uint8)
+        descs_frames = []
+        for b in range(B):
+            base = 5 + b * H * rs
+            for y in range(H):
+                buf[base + y * rs: base + y * rs + 3 * W] = frames[b, y].reshape(-1)
+        dbuf = torch.from_numpy(buf).cuda()
+        views = [torch.as_strided(dbuf, (H, W, 3), (rs, 3, 1), 5 + b * H * rs) for b in range(B)]
+        say(f"edge case {case}")
+        g = run_gpu(est, views, kw, [0, 1, 2], what=("pts", "att", "res"))
+        r, p, a = run_oracle(frames, kw, [0, 1, 2], attempts=True)
+        assert_points_equal(g["pts"], p)
+        assert_attempts_equal(g["att"], a)
+        assert_results_equal(g["res"], r)
+        return
+    say(f"edge case {case}")
+    _full_parity(torch, est, np.ascontiguousarray(frames), kw)
+
+
+def test_mixed_resolutions_in_one_batch(torch_dev, est):
+    torch = torch_dev
+    sizes = [(576, 720), (720, 1280), (1080, 1920), (480, 640), (2160, 3840)]
+    frames = [synth.make_frame(synth.HD_1080p, 100 + i, w, h)[0] for i, (h, w) in enumerate(sizes)]
+    devs = [torch.from_numpy(f).cuda() for f in frames]
+    uids = [100 + i for i in range(len(frames))]
+    say("mixed resolution batch")
+    g = run_gpu(est, devs, HD, uids, what=("pts", "res"))
+    for i, f in enumerate(frames):
+        r, p = oracle.estimate(f, oracle.params(n_hstrips=32, n_vstrips=32, attempts=1024),
+                               uids[i], with_points=True)
+        assert_points_equal(g["pts"][i:i + 1], [p])
+        assert_results_equal(g["res"][i:i + 1], [r])
+
+
+def test_frame_result_independent_of_batch(torch_dev, est, small_batch):
+    torch = torch_dev
+    frames, _ = small_batch
+    fd = _dev(torch, frames)
+    uids = [1000 + i for i in range(len(frames))]
+    whole = run_gpu(est, fd, SMALL, uids)["res"]
+    for i in (0, 5):
+        alone = run_gpu(est, fd[i:i + 1], SMALL, [uids[i]])["res"]
+        assert alone.tobytes() == whole[i:i + 1].tobytes()
+    # reversed batch order, same uids
+    rev = run_gpu(est, fd.flip(0).contiguous(), SMALL, uids[::-1])["res"]
+    assert rev[::-1].tobytes() == whole.tobytes()
+
+
+def test_repeated_runs_bitwise_equal(torch_dev, est, small_batch):
+    torch = torch_dev
+    fd = _dev(torch, small_batch[0])
+    a = run_gpu(est, fd, SMALL, list(range(8)), what=("pts", "att"))
+    b = run_gpu(est, fd, SMALL, list(range(8)), what=("pts", "att"))
+    assert a["pts"].tobytes() == b["pts"].tobytes()
+    assert a["att"].tobytes() == b["att"].tobytes()
+
+
+def test_errors_are_reported_before_enqueue(torch_dev, est):
+    torch = torch_dev
+    f = torch.zeros((1, 20, 20, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(Exception):
+        est.estimate_area(f, {"ransac_attempts": 0})
+    with pytest.raises(Exception):
+        est.estimate_area(torch.zeros((1, 8, 8, 3), dtype=torch.uint8, device="cuda"))
+    # the context stays usable
+    r = est.estimate_area(f)
+    torch.cuda.synchronize()
+    assert int(r.valid[0]) == 0 and int(r.reason[0]) == 1
+
+
+def test_tiny_budget_is_nomem_and_context_survives(torch_dev):
+    torch = torch_dev
+    from paper_2210_14771_amd import _native as N
+    e = api.Estimator(0, workspace_budget=1024)
+    f = torch.zeros((4, 64, 64, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(N.NativeError) as ei:
+        e.estimate_area(f)
+    assert ei.value.code == N.CA_E_NOMEM
+    e.close()
