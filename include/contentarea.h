@@ -173,8 +173,30 @@ int ca_strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos);
 #define CA_SG_CAPACITY 11541
 int ca_score_tables(const ca_params *p, float *sg, int32_t *sg_len, float *st, float *si);
 
+/* Schedule options of a context (ca_set_option / ca_get_option). */
+#define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_FUSED (default) or CA_SCHEDULE_SPLIT */
+#define CA_OPT_LAG 2           /* fused: frames between a frame's strip and RANSAC work (4) */
+#define CA_OPT_QUEUES 3        /* fused: work queues 1..8; 0 = 8 for >= 16 frames, else 1 */
+#define CA_OPT_GRID 4          /* fused: workgroups; 0 = as many as fit on the device */
+#define CA_OPT_SPIN_LIMIT 5    /* fused: polls before a wait gives up (a guard, 2^22) */
+#define CA_SCHEDULE_SPLIT 0    /* three launches: strips, RANSAC, selection */
+#define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
+                                  per-XCD queues so that strip scoring (memory bound)
+                                  and RANSAC (ALU bound) overlap; same results */
+
+/* Set or read an option.  CA_E_INVAL for an unknown option or value. */
+int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value);
+int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value);
+
+/* Synchronise the device and report whether every fused call so far ended
+ * its waits normally (CA_OK), or whether one gave up at the spin limit
+ * (CA_E_DEVICE: the results of that call are not to be trusted).  Clears
+ * the flag. */
+int ca_device_status(ca_ctx *ctx);
+
 /* Kernel timing (HIP events recorded on the caller's stream around each
- * kernel of each call).  Index 0: strip scoring, 1: RANSAC, 2: selection. */
+ * kernel of each call).  Index 0: strip scoring, 1: RANSAC, 2: selection;
+ * with the fused schedule the single kernel is reported at index 0. */
 typedef struct {
     double total_ms[3];      /* summed kernel durations */
     int64_t launches[3];     /* number of timed launches */

@@ -147,6 +147,24 @@ class Estimator:
         except Exception:
             pass
 
+    OPTIONS = {"schedule": N.CA_OPT_SCHEDULE, "lag": N.CA_OPT_LAG, "queues": N.CA_OPT_QUEUES,
+               "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT}
+
+    def set_option(self, name: str, value: int) -> None:
+        """Schedule options: schedule ("fused"/"split" or 1/0), lag, queues, grid, spin_limit."""
+        if name == "schedule" and isinstance(value, str):
+            value = {"fused": N.CA_SCHEDULE_FUSED, "split": N.CA_SCHEDULE_SPLIT}[value]
+        N.check(N.lib().ca_set_option(self._ctx, self.OPTIONS[name], int(value)), "ca_set_option")
+
+    def get_option(self, name: str) -> int:
+        v = C.c_int64()
+        N.check(N.lib().ca_get_option(self._ctx, self.OPTIONS[name], C.byref(v)), "ca_get_option")
+        return v.value
+
+    def device_status(self) -> None:
+        """Raise if a fused call's wait gave up at its spin limit (synchronises)."""
+        N.check(N.lib().ca_device_status(self._ctx), "ca_device_status")
+
     def profile_begin(self, max_calls: int) -> None:
         """Time each kernel of the next ``max_calls`` calls with HIP events."""
         N.check(N.lib().ca_profile_begin(self._ctx, max_calls), "ca_profile_begin")

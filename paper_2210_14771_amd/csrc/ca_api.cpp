@@ -81,10 +81,13 @@ struct Plan {
     float *lut = nullptr;
     ca_point *cand = nullptr;
     Record *rec = nullptr;
+    uint32_t *ctl = nullptr;    // fused-kernel control words (zero between calls)
     // launch facts
     int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
     bool rows_aligned = false;  // every row offset a multiple of 16
     size_t lds = 0;
+    size_t fused_lds = 0;
+    int32_t fused_grid = 0;     // resident workgroups of the fused kernel
     uint64_t last_use = 0;
 };
 
@@ -111,6 +114,13 @@ struct ca_ctx {
     std::vector<hipEvent_t> prof_events;
     int32_t prof_capacity = 0;
     int32_t prof_used = 0;
+    // schedule options (ca_set_option)
+    int64_t schedule = CA_SCHEDULE_FUSED;
+    int64_t lag = 4;
+    int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
+    int64_t grid = 0;           // 0: resident workgroups from the occupancy query
+    int64_t spin_limit = 1 << 22;
+    int n_cu = 0;
 };
 
 namespace {
@@ -220,10 +230,17 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     pl->sg_len = sg_len;
     pl->line_pitch = (int32_t)align_up((size_t)longest, 16);
     pl->lds = ca::strip_lds_bytes(sg_len, pl->line_pitch);
-    if (pl->lds > ctx->max_lds) {
+    pl->fused_lds = ca::fused_lds_bytes(sg_len, pl->line_pitch);
+    if (pl->lds > ctx->max_lds || pl->fused_lds > ctx->max_lds) {
         delete pl;
         return CA_E_UNSUPPORTED;
     }
+    int per_cu = 0;
+    if (ca::fused_occupancy(pl->fused_lds, &per_cu) != hipSuccess || per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    pl->fused_grid = per_cu * ctx->n_cu;
 
     // one device allocation: frames | strips | lut | candidates | records
     const size_t o_fd = 0;
@@ -231,7 +248,8 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     const size_t o_lut = align_up(o_strips + sizeof(int32_t) * strips.size(), 256);
     const size_t o_cand = align_up(o_lut + sizeof(float) * lut.size(), 256);
     const size_t o_rec = align_up(o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
-    const size_t total = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
+    const size_t o_ctl = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
+    const size_t total = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
 
     // evict least recently used plans until this one fits the budget
     while (ctx->used + total > ctx->budget && !ctx->plans.empty()) {
@@ -259,6 +277,7 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     pl->lut = reinterpret_cast<float *>(base + o_lut);
     pl->cand = reinterpret_cast<ca_point *>(base + o_cand);
     pl->rec = reinterpret_cast<Record *>(base + o_rec);
+    pl->ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
     // plans are built once per batch shape; a blocking upload keeps them simple
     bool ok = hipMemcpy(pl->fd, fd.data(), sizeof(FrameDev) * (size_t)n, hipMemcpyHostToDevice)
                   == hipSuccess
@@ -266,7 +285,9 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
                            hipMemcpyHostToDevice)
                      == hipSuccess
               && hipMemcpy(pl->lut, lut.data(), sizeof(float) * lut.size(), hipMemcpyHostToDevice)
-                     == hipSuccess;
+                     == hipSuccess
+              && hipMemset(pl->ctl, 0, sizeof(uint32_t) * ca::ctl_words(n)) == hipSuccess
+              && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_plan(ctx, pl);
@@ -356,6 +377,25 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
     hipEvent_t *ev = nullptr;
     if (ctx->prof_used < ctx->prof_capacity)
         ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
+    if (ctx->schedule == CA_SCHEDULE_FUSED) {
+        ca::FusedArgs fa;
+        fa.s = sa;
+        fa.r = ra;
+        fa.se = se;
+        fa.ctl = pl->ctl;
+        fa.nq = ctx->queues > 0 ? (int32_t)ctx->queues : (n >= 16 ? ca::kMaxQueues : 1);
+        fa.lag = (int32_t)ctx->lag;
+        fa.spin_limit = (uint32_t)ctx->spin_limit;
+        int grid = ctx->grid > 0 ? (int)ctx->grid : pl->fused_grid;
+        grid = (grid + fa.nq - 1) / fa.nq * fa.nq;  // equal workgroups per queue
+        // the whole call is one kernel: it is timed as the strip-scoring slot
+        if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
+            || ca::launch_fused(fa, grid, pl->fused_lds, s) != hipSuccess
+            || (ev && (hipEventRecord(ev[1], s) != hipSuccess || hipEventRecord(ev[2], s) != hipSuccess
+                       || hipEventRecord(ev[3], s) != hipSuccess)))
+            return CA_E_DEVICE;
+        return CA_OK;
+    }
     if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
         || ca::launch_strips(sa, pl->lds, s) != hipSuccess
         || (ev && hipEventRecord(ev[1], s) != hipSuccess)
@@ -415,9 +455,16 @@ int ca_create(ca_ctx **out, int device, size_t budget)
     ca_ctx *c = new (std::nothrow) ca_ctx();
     if (!c)
         return CA_E_NOMEM;
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess
+        || n_cu < 1) {
+        delete c;
+        return CA_E_DEVICE;
+    }
     c->device = device;
     c->budget = budget ? budget : ((size_t)1 << 30);
     c->max_lds = (size_t)lds;
+    c->n_cu = n_cu;
     *out = c;
     return CA_OK;
 }
@@ -531,6 +578,90 @@ int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *d
     } catch (...) {
         return CA_E_NOMEM;
     }
+}
+
+int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
+{
+    if (!ctx)
+        return CA_E_INVAL;
+    switch (option) {
+    case CA_OPT_SCHEDULE:
+        if (value != CA_SCHEDULE_SPLIT && value != CA_SCHEDULE_FUSED)
+            return CA_E_INVAL;
+        ctx->schedule = value;
+        return CA_OK;
+    case CA_OPT_LAG:
+        if (value < 0 || value > (1 << 20))
+            return CA_E_INVAL;
+        ctx->lag = value;
+        return CA_OK;
+    case CA_OPT_QUEUES:
+        if (value < 0 || value > ca::kMaxQueues)
+            return CA_E_INVAL;
+        ctx->queues = value;
+        return CA_OK;
+    case CA_OPT_GRID:
+        if (value < 0 || value > (1 << 20))
+            return CA_E_INVAL;
+        ctx->grid = value;
+        return CA_OK;
+    case CA_OPT_SPIN_LIMIT:
+        if (value < 1 || value > 0xFFFFFFFFll)
+            return CA_E_INVAL;
+        ctx->spin_limit = value;
+        return CA_OK;
+    default:
+        return CA_E_INVAL;
+    }
+}
+
+int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value)
+{
+    if (!ctx || !value)
+        return CA_E_INVAL;
+    switch (option) {
+    case CA_OPT_SCHEDULE:
+        *value = ctx->schedule;
+        return CA_OK;
+    case CA_OPT_LAG:
+        *value = ctx->lag;
+        return CA_OK;
+    case CA_OPT_QUEUES:
+        *value = ctx->queues;
+        return CA_OK;
+    case CA_OPT_GRID:
+        *value = ctx->grid;
+        return CA_OK;
+    case CA_OPT_SPIN_LIMIT:
+        *value = ctx->spin_limit;
+        return CA_OK;
+    default:
+        return CA_E_INVAL;
+    }
+}
+
+int ca_device_status(ca_ctx *ctx)
+{
+    if (!ctx)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok || hipDeviceSynchronize() != hipSuccess)
+        return CA_E_DEVICE;
+    int rc = CA_OK;
+    for (Plan *pl : ctx->plans) {
+        uint32_t err = 0;
+        if (hipMemcpy(&err, pl->ctl + ca::kCtlError, sizeof(err), hipMemcpyDeviceToHost)
+            != hipSuccess)
+            return CA_E_DEVICE;
+        if (err) {
+            rc = CA_E_DEVICE;
+            const uint32_t zero = 0;
+            if (hipMemcpy(pl->ctl + ca::kCtlError, &zero, sizeof(zero), hipMemcpyHostToDevice)
+                != hipSuccess)
+                return CA_E_DEVICE;
+        }
+    }
+    return rc;
 }
 
 int ca_check_args(const ca_frame_desc *dims, int32_t n, const ca_params *params)

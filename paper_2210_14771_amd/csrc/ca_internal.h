@@ -72,9 +72,32 @@ struct SelectArgs {
     int32_t n_frames;
 };
 
+// Control words of the fused kernel (zero between calls; the kernel restores
+// them before it ends).  Each queue ticket sits on its own 128-byte line.
+constexpr int kMaxQueues = 8;
+constexpr int kCtlLine = 32;                       // uint32 words per 128 bytes
+constexpr int kCtlRetired = kMaxQueues * kCtlLine; // workgroups that have left the loop
+constexpr int kCtlError = kCtlRetired + kCtlLine;  // nonzero: a wait hit its spin limit
+constexpr int kCtlFrames = kCtlError + kCtlLine;   // strips_done[B] then groups_done[B]
+
+inline size_t ctl_words(int n_frames) { return (size_t)kCtlFrames + 2 * (size_t)n_frames; }
+
+struct FusedArgs {
+    StripArgs s;
+    RansacArgs r;
+    SelectArgs se;
+    uint32_t *ctl;
+    int32_t nq;             // work queues (frames f with f % nq == q go to queue q)
+    int32_t lag;            // frames between a frame's strip items and its RANSAC items
+    uint32_t spin_limit;    // polls before a wait gives up and flags an error
+};
+
 size_t strip_lds_bytes(int sg_len, int line_pitch);
+size_t fused_lds_bytes(int sg_len, int line_pitch);
 hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_ransac(const RansacArgs &a, int n_frames, hipStream_t s);
 hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t fused_occupancy(size_t lds_bytes, int *blocks_per_cu);
 
 }  // namespace ca

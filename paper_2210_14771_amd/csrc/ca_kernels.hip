@@ -1,15 +1,26 @@
 // gfx950 kernels of the content-area estimator (arXiv 2210.14771, Section 2.2).
 //
-// k_strips  one workgroup per (frame, strip): stage the strip's three lines
-//           as 8-bit luma in LDS, score every pixel of both half strips
-//           (Sobel, angle to the image centre, preceding maximum; Eqs. 2-3)
-//           and keep the best pixel of each half (Section 2.2.5).  The
-//           preceding-maximum scan and the argmax -- the two operations the
-//           paper singles out as needing block-wide cooperation (Section
-//           2.2.6) -- are wave64 shuffle scans/reductions joined through LDS.
-// k_ransac  one thread per RANSAC attempt, attempts split over workgroups of
-//           256; kept points are compacted into LDS and read by broadcast.
-// k_select  merges the per-workgroup best attempts of each frame.
+// Work units
+//   strip item  (frame, strip): stage the strip's three lines as 8-bit luma in
+//               LDS, score every pixel of both half strips (Sobel, angle to the
+//               image centre, preceding maximum; Eqs. 2-3) and keep the best
+//               pixel of each half (Section 2.2.5).  The preceding-maximum scan
+//               and the argmax -- the two operations the paper singles out as
+//               needing block-wide cooperation (Section 2.2.6) -- are wave64
+//               shuffle scans/reductions joined through LDS.
+//   RANSAC item (frame, group of 256 attempts): one thread per attempt; the
+//               kept points are compacted into LDS and read by broadcast.
+//   selection   (frame): merge the best attempt of every group.
+//
+// Two schedules run the same units:
+//   k_fused     one persistent launch.  Workgroups draw tickets from per-XCD
+//               queues in which every frame's strip items precede its RANSAC
+//               items (by a lag of a few frames), so memory-bound strip work
+//               and ALU-bound RANSAC work share the CUs.  A RANSAC item waits
+//               for its frame's strip items; those hold lower tickets of the
+//               same queue and never wait, so every wait ends.  The last
+//               RANSAC group of a frame selects its circle.
+//   k_strips -> k_ransac -> k_select   three plain launches.
 //
 // Numeric contract (shared with the CPU oracle by definition, not by code):
 // integer luma and Sobel, exact integer quantisers for |g| and the angle,
@@ -22,6 +33,34 @@ namespace ca {
 namespace {
 
 constexpr uint32_t kWave = 64;
+
+// ------------------------------------------------------------ helpers -----
+
+// Device-scope relaxed accesses: they bypass the per-CU L1 and reach the
+// coherence point, so data produced by another workgroup (possibly on another
+// XCD) is read fresh without invalidating the whole L2.
+__device__ __forceinline__ uint64_t load_dev(const uint64_t *p)
+{
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_dev(const uint32_t *p)
+{
+    return __hip_atomic_load(const_cast<uint32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_dev(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_dev(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Release: this workgroup's earlier writes are visible device-wide before
+// the counter moves (the caller issues a workgroup barrier first).
+__device__ __forceinline__ uint32_t add_release(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ uint32_t luma_of(uint32_t r, uint32_t g, uint32_t b)
 {
@@ -48,6 +87,12 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
         v = v > t ? v : t;
     }
     return v;
+}
+
+__device__ __forceinline__ uint64_t pack_point(int x, int y, float s)
+{
+    return (uint64_t)(uint16_t)(int16_t)x | ((uint64_t)(uint16_t)(int16_t)y << 16)
+           | ((uint64_t)__float_as_uint(s) << 32);
 }
 
 // s_g * s_theta of one pixel from its Sobel gradient (Eq. 2, quantised).
@@ -89,13 +134,12 @@ __device__ __forceinline__ float grad_angle_score(int gx, int gy, int x, int y, 
             fd += den;
         }
         qt = dt >= 0 ? (int)f : 2048 - (int)(f + (fd != num ? 1u : 0u));
+        qt = qt < 0 ? 0 : (qt > 2048 ? 2048 : qt);
     }
     return sg[qg] * st[qt];
 }
 
-// ---------------------------------------------------------------------------
-// k_strips
-// ---------------------------------------------------------------------------
+// ------------------------------------------------------------ strips ------
 
 // Stage luma of the three lines of a horizontal strip centred on `row`.
 __device__ void load_hstrip(const uint8_t *frame, int W, int rs, int row, uint8_t *tile, int LP,
@@ -169,33 +213,19 @@ __device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
+struct StripLds {
+    const float *sg, *st, *si;  // score tables (LDS)
+    uint8_t *tile;              // 3 x line_pitch luma bytes (LDS)
+    uint32_t *scan;             // [4]
+    uint64_t *best;             // [4]
+};
+
+// One strip item: both half strips of strip s of frame f.  Ends with the two
+// candidates written (device scope) and a workgroup barrier.
+__device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
-    float *s_sg = reinterpret_cast<float *>(smem);
-    float *s_st = s_sg + a.sg_len;
-    float *s_si = s_st + kQtBins;
-    uint8_t *tile = reinterpret_cast<uint8_t *>(s_si + kLumaLevels);
-    tile = reinterpret_cast<uint8_t *>((reinterpret_cast<uintptr_t>(tile) + 15) & ~(uintptr_t)15);
-    __shared__ uint32_t s_scan[4];
-    __shared__ uint64_t s_best[4];
-
-    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
-    // so workgroup b runs on XCD b % 8; give each XCD a contiguous slice of
-    // (frame, strip) items so one frame's strips share that XCD's L2.
-    const int b = blockIdx.x;
-    const int item = (b & 7) * a.per_xcd + (b >> 3);
-    if (item >= a.n_items)
-        return;
-
     const int tid = threadIdx.x;
-    const int lut_n = a.sg_len + kQtBins + kLumaLevels;
-    for (int i = tid; i < lut_n; i += kBlock)
-        s_sg[i] = a.lut[i];
-
     const int S = a.n_h + a.n_v;
-    const int f = item / S;
-    const int s = item - f * S;
     const FrameDev d = a.fd[f];
     const uint8_t *frame = a.frames + d.offset;
     const bool horizontal = s < a.n_h;
@@ -203,9 +233,9 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     const int L = horizontal ? d.W : d.H;
     const int LP = a.line_pitch;
     if (horizontal)
-        load_hstrip(frame, d.W, d.rs, pos, tile, LP, a.aligned != 0);
+        load_hstrip(frame, d.W, d.rs, pos, c.tile, LP, a.aligned != 0);
     else
-        load_vstrip(frame, d.W, d.H, d.rs, pos, tile, LP);
+        load_vstrip(frame, d.W, d.H, d.rs, pos, c.tile, LP);
     __syncthreads();
 
     const int half = tid >> 7;
@@ -219,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     const int span = kHalfThreads * chunk;
     const int n_pass = (Lmax + span - 1) / span;
     const int sg_last = a.sg_len - 1;
-    const uint8_t *t0 = tile, *t1 = tile + LP, *t2 = tile + 2 * LP;
+    const uint8_t *t0 = c.tile, *t1 = c.tile + LP, *t2 = c.tile + 2 * LP;
 
     uint32_t carry = 0;
     uint64_t best = 0;
@@ -243,8 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
                                    - ((int)t0[im] + 2 * (int)t0[i] + (int)t0[ip]);
                 const uint32_t y1 = t1[i];
                 part[j] = horizontal
-                              ? grad_angle_score(along, across, i, pos, d.W, d.H, s_sg, sg_last, s_st)
-                              : grad_angle_score(across, along, pos, i, d.W, d.H, s_sg, sg_last, s_st);
+                              ? grad_angle_score(along, across, i, pos, d.W, d.H, c.sg, sg_last, c.st)
+                              : grad_angle_score(across, along, pos, i, d.W, d.H, c.sg, sg_last, c.st);
                 lum[j] = y1;
                 tmax = tmax > y1 ? tmax : y1;
             }
@@ -255,9 +285,9 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
         if (lane == 0)
             excl = 0;
         if (lane == kWave - 1)
-            s_scan[wv] = incl;
+            c.scan[wv] = incl;
         __syncthreads();
-        const uint32_t w0 = s_scan[2 * half], w1 = s_scan[2 * half + 1];
+        const uint32_t w0 = c.scan[2 * half], w1 = c.scan[2 * half + 1];
         if (wv & 1)
             excl = excl > w0 ? excl : w0;
         uint32_t run = carry > excl ? carry : excl;
@@ -268,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
         for (int j = 0; j < kChunk; ++j) {
             const int k = k0 + j;
             if (j < chunk && k < Lh) {
-                const float sc = part[j] * s_si[run];
+                const float sc = part[j] * c.si[run];
                 const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
                                      | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
                 best = best > key ? best : key;
@@ -278,24 +308,23 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     }
     best = wave_max_u64(best);
     if (lane == 0)
-        s_best[wv] = best;
+        c.best[wv] = best;
     __syncthreads();
     if (lt == 0) {
-        const uint64_t b0 = s_best[2 * half], b1 = s_best[2 * half + 1];
+        const uint64_t b0 = c.best[2 * half], b1 = c.best[2 * half + 1];
         const uint64_t bb = b0 > b1 ? b0 : b1;
         const int k = (int)(0xFFFFFFFFu - (uint32_t)bb);
         const int i = half == 0 ? k : L - 1 - k;
-        ca_point pt;
-        pt.x = (int16_t)(horizontal ? i : pos);
-        pt.y = (int16_t)(horizontal ? pos : i);
-        pt.score = __uint_as_float((uint32_t)(bb >> 32));
-        a.cand[(int64_t)f * (2 * S) + 2 * s + half] = pt;
+        const float sc = __uint_as_float((uint32_t)(bb >> 32));
+        store_dev(reinterpret_cast<uint64_t *>(a.cand + (int64_t)f * (2 * S) + 2 * s + half),
+                  pack_point(horizontal ? i : pos, horizontal ? pos : i, sc));
+        // publish before the workgroup signals that the strip is done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
+    __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// k_ransac
-// ---------------------------------------------------------------------------
+// ------------------------------------------------------------ RANSAC ------
 
 struct Lds {
     double2 uv[kBlock];     // shifted coordinates u, v
@@ -441,14 +470,13 @@ __device__ bool refit(const Lds &L, int n, const Band &b, double &cx, double &cy
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
+// One RANSAC item: attempts [g * 256, g * 256 + 256) of frame f.  Writes the
+// group's best attempt to its record (device scope) and ends with a barrier.
+__device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
 {
-    __shared__ Lds L;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid >> 6;
-    const int f = blockIdx.y;
-    const int g = blockIdx.x;
     const FrameDev d = a.fd[f];
     const int ox = d.W / 2, oy = d.H / 2;
 
@@ -457,10 +485,10 @@ __global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
     int x = 0, y = 0;
     float sc = 0.0f;
     if (tid < a.P) {
-        const ca_point pt = a.cand[(int64_t)f * a.P + tid];
-        x = pt.x;
-        y = pt.y;
-        sc = pt.score;
+        const uint64_t pt = load_dev(reinterpret_cast<const uint64_t *>(a.cand + (int64_t)f * a.P + tid));
+        x = (int16_t)(uint16_t)(pt & 0xFFFFu);
+        y = (int16_t)(uint16_t)((pt >> 16) & 0xFFFFu);
+        sc = __uint_as_float((uint32_t)(pt >> 32));
         int ed = x < y ? x : y;
         ed = ed < d.W - 1 - x ? ed : d.W - 1 - x;
         ed = ed < d.H - 1 - y ? ed : d.H - 1 - y;
@@ -559,7 +587,7 @@ __global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
     if (a.dbg && active)
         a.dbg[(int64_t)f * a.attempts + att] = rec;
 
-    // best kept attempt of this workgroup: keys are unique per attempt
+    // best kept attempt of this group: keys are unique per attempt
     const uint64_t wmax = wave_max_u64(key);
     if (lane == 0)
         L.wbest[wv] = wmax;
@@ -567,57 +595,222 @@ __global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
     uint64_t bmax = L.wbest[0];
     for (int w = 1; w < 4; ++w)
         bmax = bmax > L.wbest[w] ? bmax : L.wbest[w];
-    Record *out = a.rec + (int64_t)f * a.groups + g;
-    if (bmax == 0) {
-        if (tid == 0) {
-            Record r0 = {};
-            r0.n_points = n;
-            *out = r0;
-        }
-    } else if (key == bmax) {
-        Record r1 = {};
-        r1.key = key;
-        r1.cx = rec.cx;
-        r1.cy = rec.cy;
-        r1.r2 = rec.r2;
-        r1.inliers = rec.inliers;
-        r1.n_points = n;
-        *out = r1;
+    uint64_t *out = reinterpret_cast<uint64_t *>(a.rec + (int64_t)f * a.groups + g);
+    const bool writer = bmax == 0 ? tid == 0 : key == bmax;
+    if (writer) {
+        store_dev(out + 0, bmax);
+        store_dev(out + 1, (uint64_t)__double_as_longlong(bmax ? rec.cx : 0.0));
+        store_dev(out + 2, (uint64_t)__double_as_longlong(bmax ? rec.cy : 0.0));
+        store_dev(out + 3, (uint64_t)__double_as_longlong(bmax ? rec.r2 : 0.0));
+        store_dev(out + 4, (uint64_t)(uint32_t)(bmax ? rec.inliers : 0)
+                               | ((uint64_t)(uint32_t)n << 32));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
+    __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// k_select
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(64) void k_select(SelectArgs a)
+// Best circle of frame f from its groups' records (Section 2.2.5, last step).
+__device__ void select_frame(const SelectArgs &a, int f)
 {
-    const int f = blockIdx.x * 64 + threadIdx.x;
-    if (f >= a.n_frames)
-        return;
-    const Record *r = a.rec + (int64_t)f * a.groups;
+    const uint64_t *r = reinterpret_cast<const uint64_t *>(a.rec + (int64_t)f * a.groups);
+    constexpr int kWords = sizeof(Record) / sizeof(uint64_t);
     int best = 0;
-    for (int g = 1; g < a.groups; ++g)
-        if (r[g].key > r[best].key)
+    uint64_t bkey = load_dev(r);
+    for (int g = 1; g < a.groups; ++g) {
+        const uint64_t k = load_dev(r + (int64_t)g * kWords);
+        if (k > bkey) {
+            bkey = k;
             best = g;
-    const Record rb = r[best];
+        }
+    }
+    const uint64_t *rb = r + (int64_t)best * kWords;
+    const uint64_t w4 = load_dev(rb + 4);
     ca_result o = {};
-    o.n_points = rb.n_points;
-    if (rb.n_points < 3) {
+    o.n_points = (int32_t)(uint32_t)(w4 >> 32);
+    if (o.n_points < 3) {
         o.reason = 1;
-    } else if (rb.key == 0) {
+    } else if (bkey == 0) {
         o.reason = 2;
     } else {
-        const uint64_t qsum = rb.key >> 16;
-        o.cx = (float)rb.cx;
-        o.cy = (float)rb.cy;
-        o.r = (float)sqrt(rb.r2);
+        const uint64_t qsum = bkey >> 16;
+        const double cx = __longlong_as_double((long long)load_dev(rb + 1));
+        const double cy = __longlong_as_double((long long)load_dev(rb + 2));
+        const double r2 = __longlong_as_double((long long)load_dev(rb + 3));
+        o.cx = (float)cx;
+        o.cy = (float)cy;
+        o.r = (float)sqrt(r2);
         o.score = (float)((double)qsum / (16777216.0 * (double)a.P));
-        o.inliers = rb.inliers;
+        o.inliers = (int32_t)(uint32_t)w4;
         o.valid = (double)qsum >= a.threshold ? 1 : 0;
         o.reason = o.valid ? 0 : 3;
     }
     a.out[f] = o;
+}
+
+// ------------------------------------------------------------ kernels -----
+
+__device__ StripLds carve_strip_lds(uint8_t *smem, int sg_len, uint32_t *scan, uint64_t *best)
+{
+    StripLds c;
+    float *sg = reinterpret_cast<float *>(smem);
+    c.sg = sg;
+    c.st = sg + sg_len;
+    c.si = sg + sg_len + kQtBins;
+    uint8_t *tail = reinterpret_cast<uint8_t *>(sg + sg_len + kQtBins + kLumaLevels);
+    c.tile = reinterpret_cast<uint8_t *>((reinterpret_cast<uintptr_t>(tail) + 15) & ~(uintptr_t)15);
+    c.scan = scan;
+    c.best = best;
+    return c;
+}
+
+__device__ void load_tables(const StripArgs &a, uint8_t *smem)
+{
+    float *dst = reinterpret_cast<float *>(smem);
+    const int lut_n = a.sg_len + kQtBins + kLumaLevels;
+    for (int i = threadIdx.x; i < lut_n; i += kBlock)
+        dst[i] = a.lut[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_scan[4];
+    __shared__ uint64_t s_best[4];
+    // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+    // so workgroup b runs on XCD b % 8; give each XCD a contiguous slice of
+    // (frame, strip) items so one frame's strips share that XCD's L2.
+    const int b = blockIdx.x;
+    const int item = (b & 7) * a.per_xcd + (b >> 3);
+    if (item >= a.n_items)
+        return;
+    load_tables(a, smem);
+    const int S = a.n_h + a.n_v;
+    const StripLds c = carve_strip_lds(smem, a.sg_len, s_scan, s_best);
+    strip_work(a, c, item / S, item % S);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
+{
+    __shared__ Lds L;
+    ransac_work(a, L, blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void k_select(SelectArgs a)
+{
+    const int f = blockIdx.x * 64 + threadIdx.x;
+    if (f < a.n_frames)
+        select_frame(a, f);
+}
+
+struct Ticket {
+    int kind;  // 0 strip item, 1 RANSAC item, -1 none left
+    int f;     // frame
+    int idx;   // strip or attempt group
+};
+
+// Queue q serves frames q, q + nq, ...; slot t holds the strip items of its
+// t-th frame followed by the RANSAC items of its (t - lag)-th frame.
+__device__ Ticket decode_ticket(int k, int q, int nq, int B, int S, int G, int lag)
+{
+    Ticket tk = {-1, 0, 0};
+    const int Bq = (B - q + nq - 1) / nq;
+    const int Lg = lag < Bq ? lag : Bq;
+    const int a_end = Lg * S;
+    const int b_end = a_end + (Bq - Lg) * (S + G);
+    const int c_end = b_end + Lg * G;
+    int j;
+    if (k < a_end) {
+        j = k / S;
+        tk.kind = 0;
+        tk.idx = k - j * S;
+    } else if (k < b_end) {
+        const int kk = k - a_end;
+        const int slot = Lg + kk / (S + G);
+        const int r = kk - (slot - Lg) * (S + G);
+        if (r < S) {
+            j = slot;
+            tk.kind = 0;
+            tk.idx = r;
+        } else {
+            j = slot - Lg;
+            tk.kind = 1;
+            tk.idx = r - S;
+        }
+    } else if (k < c_end) {
+        const int kk = k - b_end;
+        j = Bq - Lg + kk / G;
+        tk.kind = 1;
+        tk.idx = kk - (kk / G) * G;
+    } else {
+        return tk;
+    }
+    tk.f = q + j * nq;
+    return tk;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_scan[4];
+    __shared__ uint64_t s_best[4];
+    __shared__ int s_ticket;
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int S = a.s.n_h + a.s.n_v;
+    const int G = a.r.groups;
+    const int B = a.se.n_frames;
+    const int q = (int)(blockIdx.x % (unsigned)a.nq);
+    uint32_t *strips_done = a.ctl + kCtlFrames;
+    uint32_t *groups_done = strips_done + B;
+
+    load_tables(a.s, smem);
+    const StripLds c = carve_strip_lds(smem, a.s.sg_len, s_scan, s_best);
+    Lds &L = *reinterpret_cast<Lds *>(c.tile);
+
+    for (;;) {
+        if (tid == 0)
+            s_ticket = (int)atomicAdd(a.ctl + q * kCtlLine, 1u);
+        __syncthreads();
+        const Ticket tk = decode_ticket(s_ticket, q, a.nq, B, S, G, a.lag);
+        __syncthreads();
+        if (tk.kind < 0)
+            break;
+        if (tk.kind == 0) {
+            strip_work(a.s, c, tk.f, tk.idx);
+            if (tid == 0)
+                add_release(strips_done + tk.f, 1u);
+        } else {
+            if (tid == 0) {
+                // the frame's strip items hold lower tickets of this queue and
+                // never wait, so this wait ends; the limit only guards bugs
+                uint32_t polls = 0;
+                while (load_dev(strips_done + tk.f) < (uint32_t)S) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++polls > a.spin_limit) {
+                        store_dev(a.ctl + kCtlError, 1u);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            ransac_work(a.r, L, tk.f, tk.idx);
+            if (tid == 0)
+                s_last = add_release(groups_done + tk.f, 1u) == (uint32_t)(G - 1);
+            __syncthreads();
+            if (s_last && tid == 0) {
+                select_frame(a.se, tk.f);
+                // every group of this frame has finished: rearm its counters
+                store_dev(strips_done + tk.f, 0u);
+                store_dev(groups_done + tk.f, 0u);
+            }
+        }
+    }
+    // the last workgroup out rearms the queues for the next call
+    if (tid == 0 && atomicAdd(a.ctl + kCtlRetired, 1u) == gridDim.x - 1) {
+        for (int k = 0; k < kMaxQueues; ++k)
+            store_dev(a.ctl + k * kCtlLine, 0u);
+        store_dev(a.ctl + kCtlRetired, 0u);
+    }
 }
 
 }  // namespace
@@ -625,6 +818,13 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a)
 size_t strip_lds_bytes(int sg_len, int line_pitch)
 {
     return (size_t)(sg_len + kQtBins + kLumaLevels) * sizeof(float) + 16 + 3 * (size_t)line_pitch;
+}
+
+size_t fused_lds_bytes(int sg_len, int line_pitch)
+{
+    const size_t tile = 3 * (size_t)line_pitch;
+    const size_t work = tile > sizeof(Lds) ? tile : sizeof(Lds);
+    return (size_t)(sg_len + kQtBins + kLumaLevels) * sizeof(float) + 16 + work;
 }
 
 hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s)
@@ -650,6 +850,19 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t s)
         return hipSuccess;
     hipLaunchKernelGGL(k_select, dim3((a.n_frames + 63) / 64), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s)
+{
+    if (a.se.n_frames <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t fused_occupancy(size_t lds_bytes, int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_fused, kBlock, lds_bytes);
 }
 
 }  // namespace ca

@@ -25,10 +25,13 @@ def torch_dev():
     return torch
 
 
-@pytest.fixture(scope="module")
-def est(torch_dev):
+@pytest.fixture(scope="module", params=["fused", "split"])
+def est(torch_dev, request):
     e = api.Estimator(0)
+    e.set_option("schedule", request.param)
+    say(f"schedule: {request.param}")
     yield e
+    e.device_status()
     e.close()
 
 
@@ -203,4 +206,46 @@ def test_tiny_budget_is_nomem_and_context_survives(torch_dev):
     with pytest.raises(N.NativeError) as ei:
         e.estimate_area(f)
     assert ei.value.code == N.CA_E_NOMEM
+    e.close()
+
+
+@pytest.mark.parametrize("opts", [dict(lag=0), dict(lag=1000), dict(queues=1), dict(queues=8),
+                                  dict(grid=8), dict(grid=8, queues=8, lag=0), dict(queues=3)])
+def test_fused_schedule_variants(torch_dev, small_batch, opts):
+    # every queue layout, lag and grid size must give the same bits
+    torch = torch_dev
+    frames, _ = small_batch
+    frames = np.concatenate([frames, frames[::-1].copy()])        # 16 frames
+    uids = list(range(16))
+    ref_est = api.Estimator(0)
+    ref_est.set_option("schedule", "split")
+    fd = _dev(torch, frames)
+    ref = run_gpu(ref_est, fd, SMALL, uids, what=("pts", "att", "res"))
+    ref_est.close()
+    e = api.Estimator(0)
+    for k, v in opts.items():
+        e.set_option(k, v)
+    say(f"fused variant {opts}")
+    for _ in range(2):          # a second call checks that the control words were rearmed
+        got = run_gpu(e, fd, SMALL, uids, what=("pts", "att", "res"))
+        assert got["pts"].tobytes() == ref["pts"].tobytes()
+        assert got["att"].tobytes() == ref["att"].tobytes()
+        assert got["res"].tobytes() == ref["res"].tobytes()
+    e.device_status()
+    e.close()
+
+
+def test_fused_small_batches_and_plan_switching(torch_dev, small_batch):
+    torch = torch_dev
+    frames, _ = small_batch
+    e = api.Estimator(0)
+    fd = _dev(torch, frames)
+    outs = {}
+    for n in (1, 3, 8, 1, 8, 3):
+        outs.setdefault(n, []).append(run_gpu(e, fd[:n], SMALL, list(range(n)))["res"].tobytes())
+    for n, v in outs.items():
+        assert all(x == v[0] for x in v), n
+    r, p, a = run_oracle(frames[:3], SMALL, [0, 1, 2])
+    assert_results_equal(np.frombuffer(outs[3][0], dtype=run_gpu(e, fd[:3], SMALL, [0, 1, 2])["res"].dtype), r)
+    e.device_status()
     e.close()
