@@ -178,7 +178,7 @@ int ca_score_tables(const ca_params *p, float *sg, int32_t *sg_len, float *st, f
 #define CA_OPT_LAG 2           /* fused: frames between a frame's strip and RANSAC work (4) */
 #define CA_OPT_QUEUES 3        /* fused: work queues 1..8; 0 = 8 for >= 16 frames, else 1 */
 #define CA_OPT_GRID 4          /* fused: workgroups; 0 = as many as fit on the device */
-#define CA_OPT_SPIN_LIMIT 5    /* fused: polls before a wait gives up (a guard, 2^22) */
+#define CA_OPT_SPIN_LIMIT 5    /* fused: polls before a wait gives up (a guard, 2^20) */
 #define CA_SCHEDULE_SPLIT 0    /* three launches: strips, RANSAC, selection */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
                                   per-XCD queues so that strip scoring (memory bound)

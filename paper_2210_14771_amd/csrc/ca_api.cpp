@@ -119,7 +119,7 @@ struct ca_ctx {
     int64_t lag = 4;
     int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
-    int64_t spin_limit = 1 << 22;
+    int64_t spin_limit = 1 << 20;
     int n_cu = 0;
 };
 
