@@ -62,6 +62,12 @@ __device__ __forceinline__ uint32_t add_release(uint32_t *p, uint32_t v)
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Values that steer control flow around workgroup barriers must be provably
+// wave-uniform: a value read from LDS or derived from one is treated as
+// per-lane, and a barrier under such a branch or loop lets the compiler
+// restructure the flow so that lanes pass a barrier out of step.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ uint32_t luma_of(uint32_t r, uint32_t g, uint32_t b)
 {
     return (77u * r + 150u * g + 29u * b + 128u) >> 8;
@@ -226,11 +232,13 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
 {
     const int tid = threadIdx.x;
     const int S = a.n_h + a.n_v;
+    f = uniform(f);
+    s = uniform(s);
     const FrameDev d = a.fd[f];
     const uint8_t *frame = a.frames + d.offset;
     const bool horizontal = s < a.n_h;
-    const int pos = a.strips[d.table + s];
-    const int L = horizontal ? d.W : d.H;
+    const int pos = uniform(a.strips[d.table + s]);
+    const int L = uniform(horizontal ? d.W : d.H);
     const int LP = a.line_pitch;
     if (horizontal)
         load_hstrip(frame, d.W, d.rs, pos, c.tile, LP, a.aligned != 0);
@@ -247,7 +255,7 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
     int chunk = (Lmax + kHalfThreads - 1) / kHalfThreads;
     chunk = chunk < kChunk ? chunk : kChunk;
     const int span = kHalfThreads * chunk;
-    const int n_pass = (Lmax + span - 1) / span;
+    const int n_pass = uniform((Lmax + span - 1) / span);
     const int sg_last = a.sg_len - 1;
     const uint8_t *t0 = c.tile, *t1 = c.tile + LP, *t2 = c.tile + 2 * LP;
 
@@ -477,6 +485,8 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = tid >> 6;
+    f = uniform(f);
+    g = uniform(g);
     const FrameDev d = a.fd[f];
     const int ox = d.W / 2, oy = d.H / 2;
 
@@ -766,13 +776,25 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     load_tables(a.s, smem);
     const StripLds c = carve_strip_lds(smem, a.s.sg_len, s_scan, s_best);
     Lds &L = *reinterpret_cast<Lds *>(c.tile);
+    // a workgroup can never legitimately take more items than its queue holds
+    const int Bq = (B - q + a.nq - 1) / a.nq;
+    const int max_items = Bq * (S + G);
 
-    for (;;) {
+    for (int taken = 0;; ++taken) {
+        if (taken > max_items) {
+            if (tid == 0)
+                store_dev(a.ctl + kCtlError, 2u);
+            break;
+        }
+        // The barrier before the ticket fetch keeps the single-thread work
+        // that ends an item apart from the single-thread fetch that starts
+        // the next one; merged across the loop edge they let the compiler
+        // run other lanes into the next barrier before the fetch.
+        __syncthreads();
         if (tid == 0)
             s_ticket = (int)atomicAdd(a.ctl + q * kCtlLine, 1u);
         __syncthreads();
-        const Ticket tk = decode_ticket(s_ticket, q, a.nq, B, S, G, a.lag);
-        __syncthreads();
+        const Ticket tk = decode_ticket(uniform(s_ticket), q, a.nq, B, S, G, a.lag);
         if (tk.kind < 0)
             break;
         if (tk.kind == 0) {
@@ -797,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
             if (tid == 0)
                 s_last = add_release(groups_done + tk.f, 1u) == (uint32_t)(G - 1);
             __syncthreads();
-            if (s_last && tid == 0) {
+            if (uniform(s_last) && tid == 0) {
                 select_frame(a.se, tk.f);
                 // every group of this frame has finished: rearm its counters
                 store_dev(strips_done + tk.f, 0u);
