@@ -55,11 +55,17 @@ __device__ __forceinline__ void store_dev(uint32_t *p, uint32_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Release: this workgroup's earlier writes are visible device-wide before
-// the counter moves (the caller issues a workgroup barrier first).
-__device__ __forceinline__ uint32_t add_release(uint32_t *p, uint32_t v)
+// Hand-over between workgroups.  Data that another workgroup reads is
+// written with device-scope stores (store_dev: write-through to the
+// coherence point) and read with device-scope loads (load_dev), so no L2
+// write-back or invalidate is needed: an agent-scope release fence would
+// write back the whole L2 of the XCD (buffer_wbl2), which costs more than
+// the strip itself.  The writer waits for its stores to complete before the
+// workgroup barrier; only then does one thread move the counter.
+__device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ uint32_t add_dev(uint32_t *p, uint32_t v)
 {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Values that steer control flow around workgroup barriers must be provably
@@ -326,8 +332,7 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
         const float sc = __uint_as_float((uint32_t)(bb >> 32));
         store_dev(reinterpret_cast<uint64_t *>(a.cand + (int64_t)f * (2 * S) + 2 * s + half),
                   pack_point(horizontal ? i : pos, horizontal ? pos : i, sc));
-        // publish before the workgroup signals that the strip is done
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        wait_memory();
     }
     __syncthreads();
 }
@@ -614,7 +619,7 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
         store_dev(out + 3, (uint64_t)__double_as_longlong(bmax ? rec.r2 : 0.0));
         store_dev(out + 4, (uint64_t)(uint32_t)(bmax ? rec.inliers : 0)
                                | ((uint64_t)(uint32_t)n << 32));
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        wait_memory();
     }
     __syncthreads();
 }
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
         if (tk.kind == 0) {
             strip_work(a.s, c, tk.f, tk.idx);
             if (tid == 0)
-                add_release(strips_done + tk.f, 1u);
+                add_dev(strips_done + tk.f, 1u);
         } else {
             if (tid == 0) {
                 // the frame's strip items hold lower tickets of this queue and
@@ -817,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
             __syncthreads();
             ransac_work(a.r, L, tk.f, tk.idx);
             if (tid == 0)
-                s_last = add_release(groups_done + tk.f, 1u) == (uint32_t)(G - 1);
+                s_last = add_dev(groups_done + tk.f, 1u) == (uint32_t)(G - 1);
             __syncthreads();
             if (uniform(s_last) && tid == 0) {
                 select_frame(a.se, tk.f);

@@ -249,3 +249,26 @@ def test_fused_small_batches_and_plan_switching(torch_dev, small_batch):
     assert_results_equal(np.frombuffer(outs[3][0], dtype=run_gpu(e, fd[:3], SMALL, [0, 1, 2])["res"].dtype), r)
     e.device_status()
     e.close()
+
+
+@pytest.mark.parametrize("queues", [1, 8])
+def test_fused_repeated_against_split(torch_dev, hd_batch, queues):
+    # strip candidates and attempt records cross workgroups (and XCDs) inside
+    # the fused kernel; repeated calls must reproduce the split schedule's bits
+    torch = torch_dev
+    frames, _ = hd_batch
+    fd = _dev(torch, frames)
+    uids = list(range(len(frames)))
+    split = api.Estimator(0)
+    split.set_option("schedule", "split")
+    ref = run_gpu(split, fd, HD, uids, what=("pts", "res"))
+    split.close()
+    e = api.Estimator(0)
+    e.set_option("queues", queues)
+    say(f"fused x10, queues={queues}")
+    for i in range(10):
+        got = run_gpu(e, fd, HD, uids, what=("pts", "res"))
+        assert got["pts"].tobytes() == ref["pts"].tobytes(), i
+        assert got["res"].tobytes() == ref["res"].tobytes(), i
+    e.device_status()
+    e.close()
