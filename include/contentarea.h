@@ -173,6 +173,28 @@ int ca_strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos);
 #define CA_SG_CAPACITY 11541
 int ca_score_tables(const ca_params *p, float *sg, int32_t *sg_len, float *st, float *si);
 
+/* A captured HIP graph replaying `calls` estimate calls on fixed buffers:
+ * for callers that run the same batch layout repeatedly (a serving loop, a
+ * benchmark) and want one launch instead of one per kernel. */
+typedef struct ca_graph ca_graph;
+
+/* Capture `calls` back-to-back calls of ca_estimate_area with these
+ * arguments into a graph (the plan is built first, outside the capture).
+ * The graph keeps the device pointers: the frames and `out_dev` must stay
+ * allocated, and the context alive, until ca_graph_destroy.  The context's
+ * plan for this batch is never evicted while a graph uses it.  Each launch
+ * recomputes every result from the current contents of the frames.
+ * Errors as ca_estimate_area; `calls` in [1, 4096]. */
+int ca_graph_create(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
+                    int32_t n_frames, const ca_params *params, ca_result *out_dev,
+                    int32_t calls, ca_graph **graph);
+
+/* Enqueue one replay on `stream` (a hipStream_t; NULL: default stream). */
+int ca_graph_launch(ca_graph *graph, void *stream);
+
+/* Synchronise the device and release the graph.  Null is ignored. */
+void ca_graph_destroy(ca_graph *graph);
+
 /* Schedule options of a context (ca_set_option / ca_get_option). */
 #define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_FUSED (default) or CA_SCHEDULE_SPLIT */
 #define CA_OPT_LAG 2           /* fused: frames between a frame's strip and RANSAC work (4) */

@@ -24,7 +24,8 @@ CA_SG_CAPACITY = 11541
 EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_debug_candidates", "ca_debug_attempts", "ca_check_args", "ca_strip_positions",
            "ca_score_tables", "ca_profile_begin", "ca_profile_end", "ca_set_option",
-           "ca_get_option", "ca_device_status", "ca_error_string", "ca_version")
+           "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
+           "ca_graph_destroy", "ca_error_string", "ca_version")
 CA_OPT_SCHEDULE = 1
 CA_OPT_LAG = 2
 CA_OPT_QUEUES = 3
@@ -106,6 +107,10 @@ def lib() -> C.CDLL:
         L.ca_score_tables.argtypes = [C.POINTER(Params), C.POINTER(C.c_float),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_float),
                                       C.POINTER(C.c_float)]
+        L.ca_graph_create.argtypes = run_args + [vp, i32, C.POINTER(vp)]
+        L.ca_graph_launch.argtypes = [vp, vp]
+        L.ca_graph_destroy.argtypes = [vp]
+        L.ca_graph_destroy.restype = None
         L.ca_set_option.argtypes = [vp, i32, C.c_int64]
         L.ca_get_option.argtypes = [vp, i32, C.POINTER(C.c_int64)]
         L.ca_device_status.argtypes = [vp]

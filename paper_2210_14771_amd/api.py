@@ -82,6 +82,38 @@ class Result:
         return self.raw.cpu().numpy().view(dt).reshape(-1)
 
 
+_layout_cache: dict = {}
+
+
+def _batch_layout(frames: torch.Tensor, frame_uids):
+    """Descriptors of a [B, H, W, 3] tensor computed from its strides (cached)."""
+    if frames.dtype != torch.uint8:
+        raise ValueError("frames must be uint8 [B, H, W, 3]")
+    if frames.device.type != "cuda":
+        raise ValueError("frames must be on a GPU")
+    if frames.stride(2) != 3 or frames.stride(3) != 1:
+        raise ValueError("pixels must be packed RGB (stride 3 along W, 1 along channels)")
+    B, H, W, _ = frames.shape
+    uids = tuple(range(B)) if frame_uids is None else tuple(int(u) for u in frame_uids)
+    if len(uids) != B:
+        raise ValueError("frame_uids must have one entry per frame")
+    key = (tuple(frames.shape), tuple(frames.stride()), uids)
+    descs = _layout_cache.get(key)
+    if descs is None:
+        descs = (N.FrameDesc * B)()
+        for i in range(B):
+            d = descs[i]
+            d.width, d.height = W, H
+            d.row_stride = frames.stride(1)
+            d.pixel_stride = 3
+            d.byte_offset = i * frames.stride(0)
+            d.frame_uid = uids[i] & 0xFFFFFFFFFFFFFFFF
+        if len(_layout_cache) > 64:
+            _layout_cache.clear()
+        _layout_cache[key] = descs
+    return frames.data_ptr(), descs, B, frames.device
+
+
 def _frames_layout(frames, frame_uids):
     """(base pointer, FrameDesc array, n, device) for a [B,H,W,3] tensor or a
     list of [H,W,3] tensors (mixed resolutions) on one device."""
@@ -90,6 +122,8 @@ def _frames_layout(frames, frame_uids):
             frames = frames.unsqueeze(0)
         if frames.dim() != 4 or frames.shape[-1] != 3:
             raise ValueError("frames must be uint8 [B, H, W, 3]")
+        if frames.stride(0) >= 0 and frames.shape[0] > 0:
+            return _batch_layout(frames, frame_uids)
         items = [frames[i] for i in range(frames.shape[0])]
         dev = frames.device
     else:
@@ -197,6 +231,18 @@ class Estimator:
         N.check(rc, "ca_estimate_area")
         return Result(out)
 
+    def capture(self, frames, params=None, frame_uids=None, out: torch.Tensor | None = None,
+                calls: int = 1) -> "Graph":
+        """A HIP graph replaying ``calls`` estimate calls on these buffers."""
+        base, descs, n, p, _ = self._prep(frames, params, frame_uids, None)
+        if out is None:
+            out = torch.empty((n, 8), dtype=torch.int32, device=self.device)
+        g = C.c_void_p()
+        rc = N.lib().ca_graph_create(self._ctx, C.c_void_p(base), descs, n, C.byref(p),
+                                     C.c_void_p(out.data_ptr()), calls, C.byref(g))
+        N.check(rc, "ca_graph_create")
+        return Graph(self, g, Result(out), frames)
+
     def debug_candidates(self, frames, params=None, frame_uids=None, stream=None):
         """(Result, points int16/float32 packed as int32 [B, P, 2])."""
         base, descs, n, p, s = self._prep(frames, params, frame_uids, stream)
@@ -220,6 +266,29 @@ class Estimator:
                                        C.c_void_p(s.cuda_stream))
         N.check(rc, "ca_debug_attempts")
         return Result(out), att
+
+
+class Graph:
+    """Captured estimate calls (ca_graph); keeps its buffers alive."""
+
+    def __init__(self, est: Estimator, handle, result: Result, frames):
+        self._est, self._g, self.result, self._frames = est, handle, result, frames
+
+    def launch(self, stream=None) -> Result:
+        s = stream if stream is not None else torch.cuda.current_stream(self._est.device)
+        N.check(N.lib().ca_graph_launch(self._g, C.c_void_p(s.cuda_stream)), "ca_graph_launch")
+        return self.result
+
+    def close(self):
+        if self._g is not None and self._g.value:
+            N.lib().ca_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 POINT_FIELDS = [("x", "<i2"), ("y", "<i2"), ("score", "<f4")]

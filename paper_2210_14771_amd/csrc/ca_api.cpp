@@ -88,6 +88,7 @@ struct Plan {
     size_t lds = 0;
     size_t fused_lds = 0;
     int32_t fused_grid = 0;     // resident workgroups of the fused kernel
+    int32_t pins = 0;           // graphs that replay this plan (never evicted while > 0)
     uint64_t last_use = 0;
 };
 
@@ -251,14 +252,17 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     const size_t o_ctl = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
     const size_t total = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
 
-    // evict least recently used plans until this one fits the budget
-    while (ctx->used + total > ctx->budget && !ctx->plans.empty()) {
-        size_t lru = 0;
-        for (size_t k = 1; k < ctx->plans.size(); ++k)
-            if (ctx->plans[k]->last_use < ctx->plans[lru]->last_use)
-                lru = k;
-        free_plan(ctx, ctx->plans[lru]);
-        ctx->plans.erase(ctx->plans.begin() + (long)lru);
+    // evict least recently used unpinned plans until this one fits the budget
+    while (ctx->used + total > ctx->budget) {
+        long lru = -1;
+        for (size_t k = 0; k < ctx->plans.size(); ++k)
+            if (ctx->plans[k]->pins == 0
+                && (lru < 0 || ctx->plans[k]->last_use < ctx->plans[(size_t)lru]->last_use))
+                lru = (long)k;
+        if (lru < 0)
+            break;
+        free_plan(ctx, ctx->plans[(size_t)lru]);
+        ctx->plans.erase(ctx->plans.begin() + lru);
     }
     if (ctx->used + total > ctx->budget) {
         delete pl;
@@ -298,28 +302,13 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     return CA_OK;
 }
 
-int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
-        const ca_params *params, ca_point *points_out, ca_attempt *attempts_out, ca_result *out,
-        void *stream)
+// Validated parameters and the (cached or new) plan of a batch.  The caller
+// holds a DeviceGuard.
+int get_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out)
 {
-    if (!ctx || n < 0)
-        return CA_E_INVAL;
-    if (n == 0)
-        return CA_OK;
-    if (!frames || !dims || !out)
-        return CA_E_INVAL;
-    ca_params p;
-    if (params)
-        p = *params;
-    else
-        ca_default_params(&p);
     int rc = validate(dims, n, p);
     if (rc != CA_OK)
         return rc;
-    DeviceGuard guard(ctx->device);
-    if (!guard.ok)
-        return CA_E_DEVICE;
-
     Plan *pl = nullptr;
     for (Plan *c : ctx->plans)
         if (same_key(*c, dims, n, p)) {
@@ -332,7 +321,15 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
             return rc;
     }
     pl->last_use = ++ctx->tick;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    *out = pl;
+    return CA_OK;
+}
+
+// Enqueue the whole path for one batch on stream `s`.
+int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
+            ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
+            bool timed)
+{
 
     ca::StripArgs sa;
     sa.frames = frames;
@@ -375,7 +372,7 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
     se.n_frames = n;
 
     hipEvent_t *ev = nullptr;
-    if (ctx->prof_used < ctx->prof_capacity)
+    if (timed && ctx->prof_used < ctx->prof_capacity)
         ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
     if (ctx->schedule == CA_SCHEDULE_FUSED) {
         ca::FusedArgs fa;
@@ -407,7 +404,43 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
     return CA_OK;
 }
 
+int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+        const ca_params *params, ca_point *points_out, ca_attempt *attempts_out, ca_result *out,
+        void *stream)
+{
+    if (!ctx || n < 0)
+        return CA_E_INVAL;
+    if (n == 0)
+        return CA_OK;
+    if (!frames || !dims || !out)
+        return CA_E_INVAL;
+    ca_params p;
+    if (params)
+        p = *params;
+    else
+        ca_default_params(&p);
+    int rc = validate(dims, n, p);
+    if (rc != CA_OK)
+        return rc;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    Plan *pl = nullptr;
+    rc = get_plan(ctx, dims, n, p, &pl);
+    if (rc != CA_OK)
+        return rc;
+    return enqueue(ctx, pl, frames, n, p, points_out, attempts_out, out,
+                   static_cast<hipStream_t>(stream), true);
+}
+
 }  // namespace
+
+struct ca_graph {
+    ca_ctx *ctx = nullptr;
+    Plan *plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -578,6 +611,91 @@ int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *d
     } catch (...) {
         return CA_E_NOMEM;
     }
+}
+
+int ca_graph_create(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+                    const ca_params *params, ca_result *out, int32_t calls, ca_graph **graph)
+{
+    if (!graph)
+        return CA_E_INVAL;
+    *graph = nullptr;
+    if (!ctx || n < 1 || !frames || !dims || !out || calls < 1 || calls > 4096)
+        return CA_E_INVAL;
+    ca_params p;
+    if (params)
+        p = *params;
+    else
+        ca_default_params(&p);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    Plan *pl = nullptr;
+    int rc = get_plan(ctx, dims, n, p, &pl);
+    if (rc != CA_OK)
+        return rc;
+    ca_graph *g = new (std::nothrow) ca_graph();
+    if (!g)
+        return CA_E_NOMEM;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        delete g;
+        return CA_E_DEVICE;
+    }
+    rc = CA_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = CA_E_DEVICE;
+    } else {
+        for (int32_t i = 0; i < calls && rc == CA_OK; ++i)
+            rc = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, out, s, false);
+        hipGraph_t gr = nullptr;
+        if (hipStreamEndCapture(s, &gr) != hipSuccess || !gr) {
+            rc = CA_E_DEVICE;
+        } else {
+            g->graph = gr;
+            if (rc == CA_OK && hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0) != hipSuccess)
+                rc = CA_E_DEVICE;
+        }
+    }
+    (void)hipStreamDestroy(s);
+    if (rc != CA_OK) {
+        (void)hipGetLastError();
+        if (g->exec)
+            (void)hipGraphExecDestroy(g->exec);
+        if (g->graph)
+            (void)hipGraphDestroy(g->graph);
+        delete g;
+        return rc;
+    }
+    g->ctx = ctx;
+    g->plan = pl;
+    ++pl->pins;
+    *graph = g;
+    return CA_OK;
+}
+
+int ca_graph_launch(ca_graph *g, void *stream)
+{
+    if (!g)
+        return CA_E_INVAL;
+    DeviceGuard guard(g->ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? CA_OK
+                                                                                    : CA_E_DEVICE;
+}
+
+void ca_graph_destroy(ca_graph *g)
+{
+    if (!g)
+        return;
+    {
+        DeviceGuard guard(g->ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(g->exec);
+        (void)hipGraphDestroy(g->graph);
+    }
+    --g->plan->pins;
+    delete g;
 }
 
 int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
