@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--schedule", choices=["fused", "split"], default="fused")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
+    ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
     ap.add_argument("--lag", type=int, default=None)
     ap.add_argument("--queues", type=int, default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -115,6 +116,9 @@ def main():
         est.set_option("lag", args.lag)
     if args.queues is not None:
         est.set_option("queues", args.queues)
+    if args.pipeline is not None:
+        est.set_option("pipeline", args.pipeline)
+    pipeline = est.get_option("pipeline")
     params = api.default_params(**kw)
     out = torch.empty((B, 8), dtype=torch.int32, device=dev)
     print("# warmup", file=sys.stderr, flush=True)
@@ -123,16 +127,24 @@ def main():
     torch.cuda.synchronize()
 
     K = args.steps
-    # eager calls with kernel durations recorded by the library (HIP events
-    # on the launch stream)
+    # kernel durations: HIP events recorded by the library around each kernel
+    # on the launch stream, with the whole batch in one launch per kernel
+    if args.schedule == "split":
+        est.set_option("pipeline", 1)
     est.profile_begin(K)
+    torch.cuda.synchronize()
+    for i in range(K):
+        est.estimate_area(resident[i % len(resident)], params, uids, out=out)
+    torch.cuda.synchronize()
+    kt = est.profile_end()
+    est.set_option("pipeline", pipeline)
+    # eager calls as configured
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
         est.estimate_area(resident[i % len(resident)], params, uids, out=out)
     torch.cuda.synchronize()
     elapsed_eager = time.perf_counter() - t0
-    kt = est.profile_end()
     print("# eager region done", file=sys.stderr, flush=True)
 
     # timed region: the same K calls replayed from captured HIP graphs
@@ -181,7 +193,7 @@ def main():
         strips_ms = kt["strips"]["avg_ms"]
         ransac_ms = kt["ransac"]["avg_ms"]
         kernels = {"k_" + k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]}
-                   for k, v in kt.items()}
+                   for k, v in kt.items() if k != "unused"}
         dominant = "strips" if strips_ms >= ransac_ms else "ransac"
     rl_strips = {"bound": "hbm", "achieved": algo_bytes / (strips_ms * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "traffic": None}
@@ -220,6 +232,8 @@ def main():
         "eager_value": B * K / elapsed_eager,
         "eager_ms_per_step": elapsed_eager / K * 1e3,
         "schedule": args.schedule,
+        "pipeline": pipeline if args.schedule == "split" else None,
+        "kernel_timing": "one launch per kernel for the whole batch (pipeline 1)",
         "kernels": kernels,
         "roofline": roofline,
         "roofline_other": rl_strips if dominant == "ransac" else rl_ransac,

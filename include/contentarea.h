@@ -196,15 +196,19 @@ int ca_graph_launch(ca_graph *graph, void *stream);
 void ca_graph_destroy(ca_graph *graph);
 
 /* Schedule options of a context (ca_set_option / ca_get_option). */
-#define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_FUSED (default) or CA_SCHEDULE_SPLIT */
+#define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_SPLIT (default) or CA_SCHEDULE_FUSED */
 #define CA_OPT_LAG 2           /* fused: frames between a frame's strip and RANSAC work (4) */
 #define CA_OPT_QUEUES 3        /* fused: work queues 1..8; 0 = 8 for >= 16 frames, else 1 */
 #define CA_OPT_GRID 4          /* fused: workgroups; 0 = as many as fit on the device */
 #define CA_OPT_SPIN_LIMIT 5    /* fused: polls before a wait gives up (a guard, 2^20) */
-#define CA_SCHEDULE_SPLIT 0    /* three launches: strips, RANSAC, selection */
+#define CA_OPT_PIPELINE 6      /* split: sub-batches per call, alternating over two
+                                  internal streams forked from and joined into the
+                                  caller's stream (4; 1 = everything on the caller's
+                                  stream) */
+#define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
+                                  whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
-                                  per-XCD queues so that strip scoring (memory bound)
-                                  and RANSAC (ALU bound) overlap; same results */
+                                  per-XCD queues; same results */
 
 /* Set or read an option.  CA_E_INVAL for an unknown option or value. */
 int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value);
@@ -217,8 +221,9 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value);
 int ca_device_status(ca_ctx *ctx);
 
 /* Kernel timing (HIP events recorded on the caller's stream around each
- * kernel of each call).  Index 0: strip scoring, 1: RANSAC, 2: selection;
- * with the fused schedule the single kernel is reported at index 0. */
+ * kernel of each call).  Index 0: strip scoring, 1: RANSAC with selection,
+ * 2: unused.  When a call is one fused kernel or a pipelined set of
+ * sub-batches, the whole call is reported at index 0. */
 typedef struct {
     double total_ms[3];      /* summed kernel durations */
     int64_t launches[3];     /* number of timed launches */

@@ -182,10 +182,12 @@ class Estimator:
             pass
 
     OPTIONS = {"schedule": N.CA_OPT_SCHEDULE, "lag": N.CA_OPT_LAG, "queues": N.CA_OPT_QUEUES,
-               "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT}
+               "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT,
+               "pipeline": N.CA_OPT_PIPELINE}
 
     def set_option(self, name: str, value: int) -> None:
-        """Schedule options: schedule ("fused"/"split" or 1/0), lag, queues, grid, spin_limit."""
+        """Options: schedule ("split"/"fused" or 0/1), pipeline (sub-batches of a split
+        call), lag, queues, grid, spin_limit (fused schedule)."""
         if name == "schedule" and isinstance(value, str):
             value = {"fused": N.CA_SCHEDULE_FUSED, "split": N.CA_SCHEDULE_SPLIT}[value]
         N.check(N.lib().ca_set_option(self._ctx, self.OPTIONS[name], int(value)), "ca_set_option")
@@ -207,7 +209,7 @@ class Estimator:
         """Average kernel durations (ms) of the calls timed since profile_begin."""
         t = N.KernelTimes()
         N.check(N.lib().ca_profile_end(self._ctx, C.byref(t)), "ca_profile_end")
-        names = ("strips", "ransac", "select")
+        names = ("strips", "ransac", "unused")
         return {n: {"total_ms": t.total_ms[i], "launches": int(t.launches[i]),
                     "avg_ms": t.total_ms[i] / t.launches[i] if t.launches[i] else 0.0}
                 for i, n in enumerate(names)}

@@ -4,6 +4,7 @@
 // buffers) in device memory, and enqueues the three kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -116,12 +117,17 @@ struct ca_ctx {
     int32_t prof_capacity = 0;
     int32_t prof_used = 0;
     // schedule options (ca_set_option)
-    int64_t schedule = CA_SCHEDULE_FUSED;
+    int64_t schedule = CA_SCHEDULE_SPLIT;
     int64_t lag = 4;
     int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
     int64_t spin_limit = 1 << 20;
+    int64_t pipeline = 4;       // sub-batches of a split-schedule call (1: no side streams)
     int n_cu = 0;
+    // side streams of the pipelined split schedule, with their fork/join events
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -344,6 +350,7 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     sa.per_xcd = (sa.n_items + 7) / 8;
     sa.line_pitch = pl->line_pitch;
     sa.aligned = (pl->rows_aligned && (reinterpret_cast<uintptr_t>(frames) % 16) == 0) ? 1 : 0;
+    sa.frame0 = 0;
 
     ca::RansacArgs ra;
     ra.fd = pl->fd;
@@ -362,6 +369,8 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     ra.refine = p.refine_iters;
     ra.sampler = p.sampler;
     ra.groups = pl->groups;
+    ra.frame0 = 0;
+    ra.groups_done = pl->ctl + ca::kCtlFrames + n;
 
     ca::SelectArgs se;
     se.rec = pl->rec;
@@ -393,13 +402,49 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
             return CA_E_DEVICE;
         return CA_OK;
     }
-    if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
-        || ca::launch_strips(sa, pl->lds, s) != hipSuccess
-        || (ev && hipEventRecord(ev[1], s) != hipSuccess)
-        || ca::launch_ransac(ra, n, s) != hipSuccess
-        || (ev && hipEventRecord(ev[2], s) != hipSuccess)
-        || ca::launch_select(se, s) != hipSuccess
-        || (ev && hipEventRecord(ev[3], s) != hipSuccess))
+    // strips then RANSAC for frames [f0, f1) on stream st
+    const int S = p.n_hstrips + p.n_vstrips;
+    auto launch_range = [&](int32_t f0, int32_t f1, hipStream_t st, hipEvent_t mid) {
+        ca::StripArgs a2 = sa;
+        a2.frame0 = f0;
+        a2.n_items = (f1 - f0) * S;
+        a2.per_xcd = (a2.n_items + 7) / 8;
+        ca::RansacArgs r2 = ra;
+        r2.frame0 = f0;
+        return ca::launch_strips(a2, pl->lds, st) == hipSuccess
+               && (!mid || hipEventRecord(mid, st) == hipSuccess)
+               && ca::launch_ransac(r2, se, f1 - f0, st) == hipSuccess;
+    };
+    const int32_t nsub = ctx->pipeline > 1 ? (int32_t)std::min<int64_t>(ctx->pipeline, n) : 1;
+    if (nsub == 1) {
+        if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
+            || !launch_range(0, n, s, ev ? ev[1] : nullptr)
+            || (ev && (hipEventRecord(ev[2], s) != hipSuccess || hipEventRecord(ev[3], s) != hipSuccess)))
+            return CA_E_DEVICE;
+        return CA_OK;
+    }
+    // sub-batches alternate over two side streams, forked from and joined
+    // back into the caller's stream: one sub-batch's RANSAC (ALU bound)
+    // overlaps the next one's strip loads (HBM bound); the whole call is
+    // timed in slot 0
+    const int used = nsub < 2 ? nsub : 2;
+    if ((ev && hipEventRecord(ev[0], s) != hipSuccess) || hipEventRecord(ctx->fork, s) != hipSuccess)
+        return CA_E_DEVICE;
+    for (int k = 0; k < used; ++k)
+        if (hipStreamWaitEvent(ctx->side[k], ctx->fork, 0) != hipSuccess)
+            return CA_E_DEVICE;
+    for (int32_t j = 0; j < nsub; ++j) {
+        const int32_t f0 = (int32_t)((int64_t)j * n / nsub);
+        const int32_t f1 = (int32_t)((int64_t)(j + 1) * n / nsub);
+        if (f1 > f0 && !launch_range(f0, f1, ctx->side[j & 1], nullptr))
+            return CA_E_DEVICE;
+    }
+    for (int k = 0; k < used; ++k)
+        if (hipEventRecord(ctx->join[k], ctx->side[k]) != hipSuccess
+            || hipStreamWaitEvent(s, ctx->join[k], 0) != hipSuccess)
+            return CA_E_DEVICE;
+    if (ev && (hipEventRecord(ev[1], s) != hipSuccess || hipEventRecord(ev[2], s) != hipSuccess
+               || hipEventRecord(ev[3], s) != hipSuccess))
         return CA_E_DEVICE;
     return CA_OK;
 }
@@ -498,6 +543,19 @@ int ca_create(ca_ctx **out, int device, size_t budget)
     c->budget = budget ? budget : ((size_t)1 << 30);
     c->max_lds = (size_t)lds;
     c->n_cu = n_cu;
+    {
+        DeviceGuard guard(device);
+        bool ok = guard.ok;
+        for (int k = 0; k < 2 && ok; ++k)
+            ok = hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) == hipSuccess
+                 && hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            ca_destroy(c);
+            return CA_E_DEVICE;
+        }
+    }
     *out = c;
     return CA_OK;
 }
@@ -521,6 +579,14 @@ void ca_destroy(ca_ctx *ctx)
         release_profile(ctx);
         for (Plan *p : ctx->plans)
             free_plan(ctx, p);
+        for (int k = 0; k < 2; ++k) {
+            if (ctx->side[k])
+                (void)hipStreamDestroy(ctx->side[k]);
+            if (ctx->join[k])
+                (void)hipEventDestroy(ctx->join[k]);
+        }
+        if (ctx->fork)
+            (void)hipEventDestroy(ctx->fork);
     }
     delete ctx;
 }
@@ -728,6 +794,11 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
             return CA_E_INVAL;
         ctx->spin_limit = value;
         return CA_OK;
+    case CA_OPT_PIPELINE:
+        if (value < 1 || value > 1024)
+            return CA_E_INVAL;
+        ctx->pipeline = value;
+        return CA_OK;
     default:
         return CA_E_INVAL;
     }
@@ -752,6 +823,9 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value)
         return CA_OK;
     case CA_OPT_SPIN_LIMIT:
         *value = ctx->spin_limit;
+        return CA_OK;
+    case CA_OPT_PIPELINE:
+        *value = ctx->pipeline;
         return CA_OK;
     default:
         return CA_E_INVAL;

@@ -45,6 +45,7 @@ struct StripArgs {
     int32_t per_xcd;        // items per XCD slice (grid = 8 * per_xcd)
     int32_t line_pitch;     // bytes per LDS tile row (>= longest line, multiple of 16)
     int32_t aligned;        // every frame row starts 16-byte aligned
+    int32_t frame0;         // first frame of this launch (items cover frames frame0 ..)
 };
 
 struct RansacArgs {
@@ -61,6 +62,8 @@ struct RansacArgs {
     int32_t refine;
     int32_t sampler;
     int32_t groups;         // attempt groups per frame
+    int32_t frame0;         // first frame of this launch (blockIdx.y counts from it)
+    uint32_t *groups_done;  // per frame: groups finished (the last one selects), or null
 };
 
 struct SelectArgs {
@@ -95,8 +98,7 @@ struct FusedArgs {
 size_t strip_lds_bytes(int sg_len, int line_pitch);
 size_t fused_lds_bytes(int sg_len, int line_pitch);
 hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
-hipError_t launch_ransac(const RansacArgs &a, int n_frames, hipStream_t s);
-hipError_t launch_select(const SelectArgs &a, hipStream_t s);
+hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s);
 hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t fused_occupancy(size_t lds_bytes, int *blocks_per_cu);
 

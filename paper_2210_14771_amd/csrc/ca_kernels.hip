@@ -10,7 +10,8 @@
 //               shuffle scans/reductions joined through LDS.
 //   RANSAC item (frame, group of 256 attempts): one thread per attempt; the
 //               kept points are compacted into LDS and read by broadcast.
-//   selection   (frame): merge the best attempt of every group.
+//   selection   (frame): merge the best attempt of every group; done by the
+//               group that finishes last.
 //
 // Two schedules run the same units:
 //   k_fused     one persistent launch.  Workgroups draw tickets from per-XCD
@@ -20,7 +21,10 @@
 //               for its frame's strip items; those hold lower tickets of the
 //               same queue and never wait, so every wait ends.  The last
 //               RANSAC group of a frame selects its circle.
-//   k_strips -> k_ransac -> k_select   three plain launches.
+//   k_strips -> k_ransac   two plain launches per batch (or per sub-batch,
+//               sub-batches alternating over two streams so that one
+//               sub-batch's RANSAC overlaps the next one's strip loads); the
+//               last RANSAC group of each frame selects its circle.
 //
 // Numeric contract (shared with the CPU oracle by definition, not by code):
 // integer luma and Sobel, exact integer quantisers for |g| and the angle,
@@ -701,20 +705,24 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     load_tables(a, smem);
     const int S = a.n_h + a.n_v;
     const StripLds c = carve_strip_lds(smem, a.sg_len, s_scan, s_best);
-    strip_work(a, c, item / S, item % S);
+    strip_work(a, c, a.frame0 + item / S, item % S);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a)
+// RANSAC groups of frames frame0 .. frame0 + gridDim.y - 1; the last group
+// of a frame to finish selects its circle and rearms the frame's counter.
+__global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a, SelectArgs sel)
 {
     __shared__ Lds L;
-    ransac_work(a, L, blockIdx.y, blockIdx.x);
-}
-
-__global__ __launch_bounds__(64) void k_select(SelectArgs a)
-{
-    const int f = blockIdx.x * 64 + threadIdx.x;
-    if (f < a.n_frames)
-        select_frame(a, f);
+    __shared__ int s_last;
+    const int f = a.frame0 + (int)blockIdx.y;
+    ransac_work(a, L, f, blockIdx.x);
+    if (threadIdx.x == 0)
+        s_last = add_dev(a.groups_done + f, 1u) == (uint32_t)(a.groups - 1);
+    __syncthreads();
+    if (uniform(s_last) && threadIdx.x == 0) {
+        select_frame(sel, f);
+        store_dev(a.groups_done + f, 0u);
+    }
 }
 
 struct Ticket {
@@ -776,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     const int B = a.se.n_frames;
     const int q = (int)(blockIdx.x % (unsigned)a.nq);
     uint32_t *strips_done = a.ctl + kCtlFrames;
-    uint32_t *groups_done = strips_done + B;
+    uint32_t *groups_done = a.r.groups_done;
 
     load_tables(a.s, smem);
     const StripLds c = carve_strip_lds(smem, a.s.sg_len, s_scan, s_best);
@@ -863,19 +871,11 @@ hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ransac(const RansacArgs &a, int n_frames, hipStream_t s)
+hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s)
 {
     if (n_frames <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_ransac, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_select(const SelectArgs &a, hipStream_t s)
-{
-    if (a.n_frames <= 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3((a.n_frames + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_ransac, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
     return hipGetLastError();
 }
 

@@ -25,10 +25,12 @@ def torch_dev():
     return torch
 
 
-@pytest.fixture(scope="module", params=["fused", "split"])
+@pytest.fixture(scope="module", params=["split", "split_pipe1", "fused"])
 def est(torch_dev, request):
     e = api.Estimator(0)
-    e.set_option("schedule", request.param)
+    e.set_option("schedule", "fused" if request.param == "fused" else "split")
+    if request.param == "split_pipe1":
+        e.set_option("pipeline", 1)
     say(f"schedule: {request.param}")
     yield e
     e.device_status()
@@ -272,3 +274,32 @@ def test_fused_repeated_against_split(torch_dev, hd_batch, queues):
         assert got["res"].tobytes() == ref["res"].tobytes(), i
     e.device_status()
     e.close()
+
+
+def test_graph_replays_match_eager(torch_dev, hd_batch):
+    # several replays with eager work and synchronisation between them; every
+    # replay must reproduce the eager results (no state leaks between replays)
+    torch = torch_dev
+    frames, _ = hd_batch
+    fd = _dev(torch, frames[:16])
+    fd2 = _dev(torch, frames[16:32])
+    uids = list(range(16))
+    for sched in ("split", "fused"):
+        e = api.Estimator(0)
+        e.set_option("schedule", sched)
+        p = api.default_params(**HD)
+        ref = e.estimate_area(fd, p, uids).numpy()
+        ref2 = e.estimate_area(fd2, p, uids).numpy()
+        out = torch.zeros((16, 8), dtype=torch.int32, device="cuda")
+        g = e.capture(fd, p, uids, out=out, calls=3)
+        say(f"graph replays ({sched})")
+        for i in range(4):
+            out.zero_()
+            g.launch()
+            torch.cuda.synchronize()
+            assert g.result.numpy().tobytes() == ref.tobytes(), (sched, i)
+            other = e.estimate_area(fd2, p, uids).numpy()      # eager work in between
+            assert other.tobytes() == ref2.tobytes()
+        g.close()
+        e.device_status()
+        e.close()
