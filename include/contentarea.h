@@ -203,8 +203,8 @@ void ca_graph_destroy(ca_graph *graph);
 #define CA_OPT_SPIN_LIMIT 5    /* fused: polls before a wait gives up (a guard, 2^20) */
 #define CA_OPT_PIPELINE 6      /* split: sub-batches per call, alternating over two
                                   internal streams forked from and joined into the
-                                  caller's stream (4; 1 = everything on the caller's
-                                  stream) */
+                                  caller's stream (1 = everything on the caller's
+                                  stream, the default and the fastest measured) */
 #define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from

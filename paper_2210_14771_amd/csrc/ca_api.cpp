@@ -122,7 +122,7 @@ struct ca_ctx {
     int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
     int64_t spin_limit = 1 << 20;
-    int64_t pipeline = 4;       // sub-batches of a split-schedule call (1: no side streams)
+    int64_t pipeline = 1;       // sub-batches of a split-schedule call (1: no side streams)
     int n_cu = 0;
     // side streams of the pipelined split schedule, with their fork/join events
     hipStream_t side[2] = {nullptr, nullptr};
