@@ -42,6 +42,7 @@ def parse():
                     help="estimate calls captured per HIP graph in the timed region")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
     ap.add_argument("--lag", type=int, default=None)
+    ap.add_argument("--streaming-loads", type=int, default=None, choices=[0, 1])
     ap.add_argument("--queues", type=int, default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -118,6 +119,8 @@ def main():
         est.set_option("queues", args.queues)
     if args.pipeline is not None:
         est.set_option("pipeline", args.pipeline)
+    if args.streaming_loads is not None:
+        est.set_option("streaming_loads", args.streaming_loads)
     pipeline = est.get_option("pipeline")
     params = api.default_params(**kw)
     out = torch.empty((B, 8), dtype=torch.int32, device=dev)

@@ -11,6 +11,8 @@ namespace ca {
 
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kHalfThreads = 128; // threads per half strip
+constexpr int kLanesPerAttempt = 4;                        // lanes sharing one RANSAC attempt
+constexpr int kAttemptsPerGroup = kBlock / kLanesPerAttempt; // attempts per RANSAC workgroup
 constexpr int kChunk = 16;       // most pixels one thread scores per pass
 constexpr int kQtBins = 2049;    // pseudo-angle bins, 0 .. 2048
 constexpr int kLumaLevels = 256;
@@ -46,6 +48,7 @@ struct StripArgs {
     int32_t line_pitch;     // bytes per LDS tile row (>= longest line, multiple of 16)
     int32_t aligned;        // every frame row starts 16-byte aligned
     int32_t frame0;         // first frame of this launch (items cover frames frame0 ..)
+    int32_t streaming;      // non-temporal loads for vertical strips
 };
 
 struct RansacArgs {
@@ -61,7 +64,7 @@ struct RansacArgs {
     int32_t attempts;
     int32_t refine;
     int32_t sampler;
-    int32_t groups;         // attempt groups per frame
+    int32_t groups;         // attempt groups (of kAttemptsPerGroup) per frame
     int32_t frame0;         // first frame of this launch (blockIdx.y counts from it)
     uint32_t *groups_done;  // per frame: groups finished (the last one selects), or null
 };

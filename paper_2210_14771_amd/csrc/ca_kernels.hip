@@ -198,21 +198,32 @@ __device__ void load_hstrip(const uint8_t *frame, int W, int rs, int row, uint8_
 }
 
 // Stage luma of the three columns of a vertical strip centred on `col`.
+// `streaming` marks the row loads non-temporal.
 __device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col, uint8_t *tile,
-                            int LP)
+                            int LP, bool streaming)
 {
     const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
     const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
     for (int y = threadIdx.x; y < H; y += kBlock) {
         const uint8_t *p = frame + (int64_t)y * rs + 3 * (col - 1);
         const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
-        const uintptr_t al = addr & ~(uintptr_t)3;
+        const uint32_t sh = (uint32_t)(addr & 3);
+        const uintptr_t al = addr - sh;
         uint32_t b03, b47, b8;
         if (al >= fstart && al + 12 <= fend) {
-            // the 9 bytes lie inside 3 aligned dwords; extract with v_alignbyte
-            const uint32_t *w = reinterpret_cast<const uint32_t *>(al);
-            const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-            const uint32_t sh = (uint32_t)(addr - al);
+            // the 9 bytes lie inside 3 aligned dwords; extract with v_alignbyte.
+            // (pointer arithmetic, not integer casts, keeps the global address space)
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(p - sh);
+            uint32_t w0, w1, w2;
+            if (streaming) {
+                w0 = __builtin_nontemporal_load(w);
+                w1 = __builtin_nontemporal_load(w + 1);
+                w2 = __builtin_nontemporal_load(w + 2);
+            } else {
+                w0 = w[0];
+                w1 = w[1];
+                w2 = w[2];
+            }
             b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
             b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
             b8 = (w2 >> (8 * sh)) & 0xFFu;
@@ -253,7 +264,7 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
     if (horizontal)
         load_hstrip(frame, d.W, d.rs, pos, c.tile, LP, a.aligned != 0);
     else
-        load_vstrip(frame, d.W, d.H, d.rs, pos, c.tile, LP);
+        load_vstrip(frame, d.W, d.H, d.rs, pos, c.tile, LP, a.streaming != 0);
     __syncthreads();
 
     const int half = tid >> 7;
@@ -442,11 +453,30 @@ __device__ __forceinline__ Band make_band(double cx, double cy, double r2, doubl
     return b;
 }
 
-// One inlier pass + Coope least-squares refit (Section 2.2.5).
-__device__ bool refit(const Lds &L, int n, const Band &b, double &cx, double &cy, double &r2)
+// Sum over the 4 lanes of a quad (the lanes of one attempt).  The partial
+// sums are integers below 2^53, so every order gives the same exact total.
+template <int kCtrl>
+__device__ __forceinline__ double quad_xor(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double quad_sum(double v)
+{
+    static_assert(kLanesPerAttempt == 4, "quad reduction");
+    v += quad_xor<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    v += quad_xor<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    return v;
+}
+
+// One inlier pass + Coope least-squares refit (Section 2.2.5).  Lane `sub`
+// of the attempt's quad takes points sub, sub + 4, ...
+__device__ bool refit(const Lds &L, int n, int sub, const Band &b, double &cx, double &cy,
+                      double &r2)
 {
     double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = sub; i < n; i += kLanesPerAttempt) {
         const double2 p = L.uv[i];
         const double du = p.x - b.cx;
         const double dv = p.y - b.cy;
@@ -463,6 +493,15 @@ __device__ bool refit(const Lds &L, int n, const Band &b, double &cx, double &cy
         S7 = fma(w, m3.x, S7);
         S8 = fma(w, m3.y, S8);
     }
+    S0 = quad_sum(S0);
+    S1 = quad_sum(S1);
+    S2 = quad_sum(S2);
+    S3 = quad_sum(S3);
+    S4 = quad_sum(S4);
+    S5 = quad_sum(S5);
+    S6 = quad_sum(S6);
+    S7 = quad_sum(S7);
+    S8 = quad_sum(S8);
     const int64_t m = (int64_t)S0;
     if (m < 3)
         return false;
@@ -487,8 +526,9 @@ __device__ bool refit(const Lds &L, int n, const Band &b, double &cx, double &cy
     return true;
 }
 
-// One RANSAC item: attempts [g * 256, g * 256 + 256) of frame f.  Writes the
-// group's best attempt to its record (device scope) and ends with a barrier.
+// One RANSAC item: attempts [g * 64, g * 64 + 64) of frame f, four lanes per
+// attempt.  Writes the group's best attempt to its record (device scope) and
+// ends with a barrier.
 __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
 {
     const int tid = threadIdx.x;
@@ -537,7 +577,8 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
     }
     __syncthreads();
 
-    const int att = g * kBlock + tid;
+    const int sub = tid & (kLanesPerAttempt - 1);
+    const int att = g * kAttemptsPerGroup + tid / kLanesPerAttempt;
     const bool active = att < a.attempts;
     uint64_t key = 0;
     ca_attempt rec = {};
@@ -565,7 +606,7 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
                 r2 = ddx * ddx + ddy * ddy;
                 for (int k = 1; k <= a.refine; ++k) {
                     const Band bd = make_band(cx, cy, r2, a.t_ri);
-                    if (!refit(L, n, bd, cx, cy, r2)) {
+                    if (!refit(L, n, sub, bd, cx, cy, r2)) {
                         rec.fail_stage = k;
                         ok = false;
                         break;
@@ -575,7 +616,7 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
             if (ok) {
                 const Band bd = make_band(cx, cy, r2, a.t_ri);
                 double cnt = 0, qs = 0;
-                for (int i = 0; i < n; ++i) {
+                for (int i = sub; i < n; i += kLanesPerAttempt) {
                     const double2 p = L.uv[i];
                     const double du = p.x - bd.cx;
                     const double dv = p.y - bd.cy;
@@ -584,6 +625,8 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
                     cnt += w;
                     qs = fma(w, L.q[i], qs);
                 }
+                cnt = quad_sum(cnt);
+                qs = quad_sum(qs);
                 const double acx = (double)ox + cx;
                 const double acy = (double)oy + cy;
                 const double r = sqrt(r2);
@@ -598,12 +641,12 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
                 rec.cx = acx;
                 rec.cy = acy;
                 rec.r2 = r2;
-                if (kept)
+                if (kept && sub == 0)
                     key = (rec.qsum << 16) | (uint64_t)(0xFFFFu - (uint32_t)att);
             }
         }
     }
-    if (a.dbg && active)
+    if (a.dbg && active && sub == 0)
         a.dbg[(int64_t)f * a.attempts + att] = rec;
 
     // best kept attempt of this group: keys are unique per attempt
@@ -670,13 +713,15 @@ __device__ void select_frame(const SelectArgs &a, int f)
 
 __device__ StripLds carve_strip_lds(uint8_t *smem, int sg_len, uint32_t *scan, uint64_t *best)
 {
+    // offsets from the LDS base (no integer casts: they would turn LDS
+    // accesses into generic ones)
     StripLds c;
     float *sg = reinterpret_cast<float *>(smem);
     c.sg = sg;
     c.st = sg + sg_len;
     c.si = sg + sg_len + kQtBins;
-    uint8_t *tail = reinterpret_cast<uint8_t *>(sg + sg_len + kQtBins + kLumaLevels);
-    c.tile = reinterpret_cast<uint8_t *>((reinterpret_cast<uintptr_t>(tail) + 15) & ~(uintptr_t)15);
+    const int tables = (sg_len + kQtBins + kLumaLevels) * (int)sizeof(float);
+    c.tile = smem + ((tables + 15) & ~15);
     c.scan = scan;
     c.best = best;
     return c;
