@@ -37,12 +37,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU work of the oracle sample")
     ap.add_argument("--batches", type=int, default=2, help="distinct resident batches rotated")
-    ap.add_argument("--schedule", choices=["fused", "split"], default="fused")
+    ap.add_argument("--schedule", choices=["fused", "split"], default="split")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
     ap.add_argument("--lag", type=int, default=None)
-    ap.add_argument("--streaming-loads", type=int, default=None, choices=[0, 1])
     ap.add_argument("--queues", type=int, default=None)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -119,8 +118,6 @@ def main():
         est.set_option("queues", args.queues)
     if args.pipeline is not None:
         est.set_option("pipeline", args.pipeline)
-    if args.streaming_loads is not None:
-        est.set_option("streaming_loads", args.streaming_loads)
     pipeline = est.get_option("pipeline")
     params = api.default_params(**kw)
     out = torch.empty((B, 8), dtype=torch.int32, device=dev)

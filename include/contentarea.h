@@ -205,7 +205,6 @@ void ca_graph_destroy(ca_graph *graph);
                                   internal streams forked from and joined into the
                                   caller's stream (1 = everything on the caller's
                                   stream, the default and the fastest measured) */
-#define CA_OPT_STREAMING_LOADS 7 /* 1: vertical-strip rows loaded non-temporally (0) */
 #define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from

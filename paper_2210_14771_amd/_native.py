@@ -32,7 +32,6 @@ CA_OPT_QUEUES = 3
 CA_OPT_GRID = 4
 CA_OPT_SPIN_LIMIT = 5
 CA_OPT_PIPELINE = 6
-CA_OPT_STREAMING_LOADS = 7
 CA_SCHEDULE_SPLIT = 0
 CA_SCHEDULE_FUSED = 1
 

@@ -183,7 +183,7 @@ class Estimator:
 
     OPTIONS = {"schedule": N.CA_OPT_SCHEDULE, "lag": N.CA_OPT_LAG, "queues": N.CA_OPT_QUEUES,
                "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT,
-               "pipeline": N.CA_OPT_PIPELINE, "streaming_loads": N.CA_OPT_STREAMING_LOADS}
+               "pipeline": N.CA_OPT_PIPELINE}
 
     def set_option(self, name: str, value: int) -> None:
         """Options: schedule ("split"/"fused" or 0/1), pipeline (sub-batches of a split

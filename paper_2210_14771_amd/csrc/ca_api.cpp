@@ -123,7 +123,6 @@ struct ca_ctx {
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
     int64_t spin_limit = 1 << 20;
     int64_t pipeline = 1;       // sub-batches of a split-schedule call (1: no side streams)
-    int64_t vstream = 0;        // non-temporal vertical-strip loads
     int n_cu = 0;
     // side streams of the pipelined split schedule, with their fork/join events
     hipStream_t side[2] = {nullptr, nullptr};
@@ -352,7 +351,6 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     sa.line_pitch = pl->line_pitch;
     sa.aligned = (pl->rows_aligned && (reinterpret_cast<uintptr_t>(frames) % 16) == 0) ? 1 : 0;
     sa.frame0 = 0;
-    sa.streaming = (int32_t)ctx->vstream;
 
     ca::RansacArgs ra;
     ra.fd = pl->fd;
@@ -801,11 +799,6 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
             return CA_E_INVAL;
         ctx->pipeline = value;
         return CA_OK;
-    case CA_OPT_STREAMING_LOADS:
-        if (value != 0 && value != 1)
-            return CA_E_INVAL;
-        ctx->vstream = value;
-        return CA_OK;
     default:
         return CA_E_INVAL;
     }
@@ -833,9 +826,6 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value)
         return CA_OK;
     case CA_OPT_PIPELINE:
         *value = ctx->pipeline;
-        return CA_OK;
-    case CA_OPT_STREAMING_LOADS:
-        *value = ctx->vstream;
         return CA_OK;
     default:
         return CA_E_INVAL;

@@ -48,7 +48,6 @@ struct StripArgs {
     int32_t line_pitch;     // bytes per LDS tile row (>= longest line, multiple of 16)
     int32_t aligned;        // every frame row starts 16-byte aligned
     int32_t frame0;         // first frame of this launch (items cover frames frame0 ..)
-    int32_t streaming;      // non-temporal loads for vertical strips
 };
 
 struct RansacArgs {

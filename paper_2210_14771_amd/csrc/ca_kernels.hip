@@ -198,9 +198,8 @@ __device__ void load_hstrip(const uint8_t *frame, int W, int rs, int row, uint8_
 }
 
 // Stage luma of the three columns of a vertical strip centred on `col`.
-// `streaming` marks the row loads non-temporal.
 __device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col, uint8_t *tile,
-                            int LP, bool streaming)
+                            int LP)
 {
     const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
     const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
@@ -214,16 +213,7 @@ __device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col,
             // the 9 bytes lie inside 3 aligned dwords; extract with v_alignbyte.
             // (pointer arithmetic, not integer casts, keeps the global address space)
             const uint32_t *w = reinterpret_cast<const uint32_t *>(p - sh);
-            uint32_t w0, w1, w2;
-            if (streaming) {
-                w0 = __builtin_nontemporal_load(w);
-                w1 = __builtin_nontemporal_load(w + 1);
-                w2 = __builtin_nontemporal_load(w + 2);
-            } else {
-                w0 = w[0];
-                w1 = w[1];
-                w2 = w[2];
-            }
+            const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
             b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
             b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
             b8 = (w2 >> (8 * sh)) & 0xFFu;
@@ -264,7 +254,7 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
     if (horizontal)
         load_hstrip(frame, d.W, d.rs, pos, c.tile, LP, a.aligned != 0);
     else
-        load_vstrip(frame, d.W, d.H, d.rs, pos, c.tile, LP, a.streaming != 0);
+        load_vstrip(frame, d.W, d.H, d.rs, pos, c.tile, LP);
     __syncthreads();
 
     const int half = tid >> 7;
