@@ -61,6 +61,25 @@ def ransac_flops(n_points, attempts: int, refine: int) -> float:
     return float(sum(attempts * n * (refine * 23 + 9) for n in n_points if n >= 3))
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2210_14771_amd", "csrc", "ca_kernels.hip")
+    summary = os.path.join(ROOT, "profiles", "k_strips_64x1080p_hbm_traffic.md")
+    try:
+        text = open(summary).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch " + kernel + r" (\d+)", text)
+    h = re.search(r"source_sha256_prefix ([0-9a-f]+)", text)
+    if not m or not h or not sha.startswith(h.group(1)):
+        return None
+    return int(m.group(1))
+
+
 def cpu_baseline(frames, kw, target_cpu_s: float):
     import oracle
     threads = max(1, min(os.cpu_count() or 1, 16))
@@ -195,8 +214,13 @@ def main():
         kernels = {"k_" + k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]}
                    for k, v in kt.items() if k != "unused"}
         dominant = "strips" if strips_ms >= ransac_ms else "ransac"
+    traffic = measured_traffic("k_strips") if args.schedule == "split" else None
     rl_strips = {"bound": "hbm", "achieved": algo_bytes / (strips_ms * 1e-3) / 1e9,
-                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "traffic": None}
+                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "traffic": traffic,
+                 "traffic_note": "bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                 "copy-calibrated (profiles/k_strips_64x1080p_hbm_traffic.md)"}
+    if traffic:
+        rl_strips["traffic_gbps"] = traffic / (strips_ms * 1e-3) / 1e9
     rl_strips["frac"] = rl_strips["achieved"] / rl_strips["peak"]
     rl_ransac = {"bound": "alu", "achieved": flops / (ransac_ms * 1e-3) / 1e12,
                  "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None}
