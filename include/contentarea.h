@@ -83,7 +83,13 @@ typedef struct {
     int32_t ransac_attempts; /* attempts per frame, [1, CA_MAX_ATTEMPTS] (256) */
     int32_t sampler;         /* 0 random triples; 1 the a-th triple in lexicographic order */
     uint64_t seed;           /* key of the counter-based sampler */
+    int32_t scorer;          /* CA_SCORER_HANDCRAFTED (Section 2.2.3) or CA_SCORER_LEARNED
+                                (Section 2.2.4; needs ca_set_model; t_px is not applied) */
+    int32_t reserved;
 } ca_params;
+
+#define CA_SCORER_HANDCRAFTED 0
+#define CA_SCORER_LEARNED 1
 
 /* Result per frame (32 bytes). */
 typedef struct {
@@ -154,6 +160,38 @@ int ca_debug_candidates(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_d
 int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
                       int32_t n_frames, const ca_params *params, ca_attempt *attempts_dev,
                       ca_result *out_dev, void *stream);
+
+/* Learned strip scorer (Section 2.2.4): a 1-D CNN along each strip.  Input
+ * at each strip position: the R, G, B values v of 8 lines (pos-3 .. pos+4,
+ * clamped) as (v - 128) / 64, 24 channels; four width-5 convolutions
+ * 24 -> 16 -> 32 -> 32 -> 16 with ReLU and zero padding beyond the strip ends,
+ * a 1x1 convolution to one logit, score = sigmoid(logit).  Weights and
+ * hidden activations are bfloat16, sums float32.
+ *
+ * Model file: CA_CNN_PARAMS float32 values in the order W1[16][24][5], b1[16],
+ * W2[32][16][5], b2[32], W3[32][32][5], b3[32], W4[16][32][5], b4[16],
+ * W5[1][16][1], b5[1] (W[out][in][tap]); weights are rounded to bfloat16
+ * when loaded. */
+#define CA_CNN_PARAMS 12273
+#define CA_CNN_WINDOW 128      /* positions per window */
+#define CA_CNN_OUTPUTS 112     /* exact logits per window: positions 8 .. 119 */
+
+/* Load (host pointer) the model used by scorer CA_SCORER_LEARNED.  Blocking. */
+int ca_set_model(ca_ctx *ctx, const float *params_host, int32_t n_params);
+
+/* Logits of windows (for tests and training data checks): `windows_dev` is
+ * uint8 [n][8][CA_CNN_WINDOW][3] (line, position, colour); `range_dev` is
+ * int32 [n][2]: positions lo .. hi-1 of each window lie inside its strip (the
+ * others are zero in every layer's input).  Writes float32
+ * [n][CA_CNN_OUTPUTS] logits of positions 8 .. 119 (values at positions
+ * outside the strip are unspecified).  Needs ca_set_model. */
+int ca_cnn_window_logits(ca_ctx *ctx, const uint8_t *windows_dev, const int32_t *range_dev,
+                         int32_t n_windows, float *logits_dev, void *stream);
+
+/* Diagnostic: one v_mfma_f32_16x16x32_bf16 on fixed integer inputs
+ * A[m][k] = (7m + 3k) mod 11 - 5, B[k][n] = (5k + 2n) mod 13 - 6; writes the
+ * 16 x 16 product row-major to `out_dev` (256 floats). */
+int ca_selftest_mfma(ca_ctx *ctx, float *out_dev, void *stream);
 
 /* Host-side helpers (no device work). */
 

@@ -79,12 +79,20 @@ def conv_same(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
     return y
 
 
-def forward(x: np.ndarray, params, store_bf16: bool = True) -> dict:
-    """Activations of one strip: h[0] = input, h[1..4] hidden, z logit, s score."""
+def forward(x: np.ndarray, params, store_bf16: bool = True, mask=None) -> dict:
+    """Activations of one strip: h[0] = input, h[1..4] hidden, z logit, s score.
+
+    `mask` (optional, boolean per position) marks the positions that belong
+    to the strip; the others are zero in every layer's input, as beyond the
+    ends of a strip."""
+    if mask is not None:
+        x = np.where(mask[None, :], x, 0.0)
     h = [x]
     pre = []
     for li, (w, b) in enumerate(params[:-1]):
         a = conv_same(h[-1], w, b)
+        if mask is not None:
+            a = np.where(mask[None, :], a, 0.0)
         pre.append(a)
         r = np.maximum(a, 0.0)
         h.append(bf16(r) if store_bf16 else r)
@@ -116,7 +124,7 @@ def conv_backward(x: np.ndarray, w: np.ndarray, dy: np.ndarray):
     return dxp[:, half:half + L], dw, db
 
 
-def backward(cache: dict, params, dz: np.ndarray):
+def backward(cache: dict, params, dz: np.ndarray, mask=None):
     """Parameter gradients for an upstream gradient dz on the logits."""
     h = cache["h"]
     grads = [None] * len(params)
@@ -126,21 +134,63 @@ def backward(cache: dict, params, dz: np.ndarray):
     for li in range(len(params) - 2, -1, -1):
         w, b = params[li]
         dpre = dx * (cache["pre"][li] > 0)
+        if mask is not None:
+            dpre = np.where(mask[None, :], dpre, 0.0)
         dx, dw, db = conv_backward(h[li], w, dpre)
         grads[li] = (dw, db)
     return grads
 
 
-def loss_and_grads(xs, ts, params, store_bf16: bool = True):
-    """Mean soft-BCE over all positions of a list of strips, and its gradients."""
-    total = sum(len(t) for t in ts)
+def flat_params(params) -> np.ndarray:
+    """Parameters in the model-file order: W1, b1, W2, b2, ..., W5, b5."""
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
+
+
+def unflat_params(v: np.ndarray):
+    out, at = [], 0
+    for ci, co, k in LAYERS:
+        w = v[at:at + co * ci * k].reshape(co, ci, k)
+        at += co * ci * k
+        b = v[at:at + co]
+        at += co
+        out.append((np.asarray(w, dtype=np.float64), np.asarray(b, dtype=np.float64)))
+    return out
+
+
+WINDOW = 128      # positions of one window
+HALO = 8          # receptive-field radius of the network
+OUTPUTS = WINDOW - 2 * HALO
+
+
+def window_forward(win_u8: np.ndarray, lo: int, hi: int, params) -> np.ndarray:
+    """Logits of the OUTPUTS central positions of one window [8, WINDOW, 3]
+    whose positions lo .. hi-1 belong to the strip (NaN where outside)."""
+    x = (win_u8.astype(np.float64) - 128.0) / 64.0            # [8, W, 3]
+    x = x.transpose(0, 2, 1).reshape(N_LINES * 3, WINDOW)
+    mask = np.zeros(WINDOW, dtype=bool)
+    mask[lo:hi] = True
+    z = forward(x, params, True, mask)["z"][HALO:WINDOW - HALO]
+    return np.where(mask[HALO:WINDOW - HALO], z, np.nan)
+
+
+def loss_and_grads(xs, ts, params, store_bf16: bool = True, masks=None, weights=None):
+    """Mean soft-BCE over all weighted positions of a list of strips, and its
+    gradients.  `weights` (optional, per strip, per position, 0/1) selects the
+    positions that carry a loss; `masks` marks positions inside the strip."""
+    if weights is None:
+        weights = [np.ones(len(t)) for t in ts]
+    if masks is None:
+        masks = [None] * len(ts)
+    total = sum(float(w.sum()) for w in weights)
     loss = 0.0
     acc = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
-    for x, t in zip(xs, ts):
-        c = forward(x, params, store_bf16)
-        loss += bce(c["s"], t) * len(t) / total
-        dz = (c["s"] - t) / total
-        g = backward(c, params, dz)
+    for x, t, m, wt in zip(xs, ts, masks, weights):
+        c = forward(x, params, store_bf16, m)
+        eps = 1e-12
+        s = c["s"]
+        loss += float(np.sum(-wt * (t * np.log(s + eps) + (1 - t) * np.log(1 - s + eps)))) / total
+        dz = wt * (s - t) / total
+        g = backward(c, params, dz, m)
         acc = [(a[0] + gw, a[1] + gb) for a, (gw, gb) in zip(acc, g)]
     return loss, acc
 
@@ -157,3 +207,31 @@ def edge_target(length: int, pos: int, horizontal: bool, circle, sigma: float = 
     else:
         rho = np.hypot(pos - cx, k - cy)
     return np.exp(-((rho - r) ** 2) / (2.0 * sigma * sigma))
+
+
+def strip_logits(frame: np.ndarray, pos: int, horizontal: bool, params) -> np.ndarray:
+    """Logits of every position of one strip (the whole line, zero padded)."""
+    return forward(strip_input(frame, pos, horizontal), params, True)["z"]
+
+
+def learned_half_strip_scores(frame: np.ndarray, params, n_h: int, n_v: int, alpha: float = 8.0):
+    """Per half strip, in canonical candidate order: (xs, ys, scores) of all
+    pixels in scan order (k = 0 at the outer edge), scores = sigmoid(logit)."""
+    import oracle as ora
+    h, w = frame.shape[:2]
+    rows = ora.strip_positions(h, n_h, alpha)
+    cols = ora.strip_positions(w, n_v, alpha)
+    out = []
+    for i, r in enumerate(rows):
+        s = 1.0 / (1.0 + np.exp(-strip_logits(frame, int(r), True, params)))
+        k = np.arange(w // 2)
+        out.append((k, np.full_like(k, r), s[k]))
+        k2 = np.arange(w - w // 2)
+        out.append((w - 1 - k2, np.full_like(k2, r), s[w - 1 - k2]))
+    for j, c in enumerate(cols):
+        s = 1.0 / (1.0 + np.exp(-strip_logits(frame, int(c), False, params)))
+        k = np.arange(h // 2)
+        out.append((np.full_like(k, c), k, s[k]))
+        k2 = np.arange(h - h // 2)
+        out.append((np.full_like(k2, c), h - 1 - k2, s[h - 1 - k2]))
+    return out

@@ -25,7 +25,13 @@ EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_debug_candidates", "ca_debug_attempts", "ca_check_args", "ca_strip_positions",
            "ca_score_tables", "ca_profile_begin", "ca_profile_end", "ca_set_option",
            "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
-           "ca_graph_destroy", "ca_error_string", "ca_version")
+           "ca_graph_destroy", "ca_set_model", "ca_cnn_window_logits", "ca_selftest_mfma",
+           "ca_error_string", "ca_version")
+CA_SCORER_HANDCRAFTED = 0
+CA_SCORER_LEARNED = 1
+CA_CNN_PARAMS = 12273
+CA_CNN_WINDOW = 128
+CA_CNN_OUTPUTS = 112
 CA_OPT_SCHEDULE = 1
 CA_OPT_LAG = 2
 CA_OPT_QUEUES = 3
@@ -48,7 +54,8 @@ class Params(C.Structure):
                 ("t_ps", C.c_double), ("t_cs", C.c_double), ("t_px", C.c_int32),
                 ("refine_iters", C.c_int32), ("t_ri", C.c_double), ("r_min", C.c_double),
                 ("r_max", C.c_double), ("d_max", C.c_double), ("ransac_attempts", C.c_int32),
-                ("sampler", C.c_int32), ("seed", C.c_uint64)]
+                ("sampler", C.c_int32), ("seed", C.c_uint64), ("scorer", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ResultRec(C.Structure):
@@ -112,6 +119,9 @@ def lib() -> C.CDLL:
         L.ca_graph_launch.argtypes = [vp, vp]
         L.ca_graph_destroy.argtypes = [vp]
         L.ca_graph_destroy.restype = None
+        L.ca_set_model.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.ca_cnn_window_logits.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.ca_selftest_mfma.argtypes = [vp, vp, vp]
         L.ca_set_option.argtypes = [vp, i32, C.c_int64]
         L.ca_get_option.argtypes = [vp, i32, C.POINTER(C.c_int64)]
         L.ca_device_status.argtypes = [vp]

@@ -201,6 +201,36 @@ class Estimator:
         """Raise if a fused call's wait gave up at its spin limit (synchronises)."""
         N.check(N.lib().ca_device_status(self._ctx), "ca_device_status")
 
+    def set_model(self, params) -> None:
+        """Load the learned scorer (CA_CNN_PARAMS float32 values, model-file order)."""
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        N.check(N.lib().ca_set_model(self._ctx, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+                "ca_set_model")
+
+    def cnn_window_logits(self, windows: torch.Tensor, ranges: torch.Tensor,
+                          stream=None) -> torch.Tensor:
+        """Logits [n, 112] of uint8 windows [n, 8, 128, 3] with int32 ranges [n, 2]."""
+        if windows.dtype != torch.uint8 or tuple(windows.shape[1:]) != (8, N.CA_CNN_WINDOW, 3):
+            raise ValueError("windows must be uint8 [n, 8, 128, 3]")
+        windows = windows.contiguous()
+        ranges = ranges.to(torch.int32).contiguous()
+        n = windows.shape[0]
+        z = torch.empty((n, N.CA_CNN_OUTPUTS), dtype=torch.float32, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        N.check(N.lib().ca_cnn_window_logits(self._ctx, C.c_void_p(windows.data_ptr()),
+                                             C.c_void_p(ranges.data_ptr()), n,
+                                             C.c_void_p(z.data_ptr()), C.c_void_p(s.cuda_stream)),
+                "ca_cnn_window_logits")
+        return z
+
+    def selftest_mfma(self) -> torch.Tensor:
+        out = torch.empty((16, 16), dtype=torch.float32, device=self.device)
+        s = torch.cuda.current_stream(self.device)
+        N.check(N.lib().ca_selftest_mfma(self._ctx, C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(s.cuda_stream)), "ca_selftest_mfma")
+        return out
+
     def profile_begin(self, max_calls: int) -> None:
         """Time each kernel of the next ``max_calls`` calls with HIP events."""
         N.check(N.lib().ca_profile_begin(self._ctx, max_calls), "ca_profile_begin")

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB_PATH = os.path.join(OUT_DIR, "libcontentarea.so")
-SOURCES = ["ca_api.cpp", "ca_kernels.hip"]
+SOURCES = ["ca_api.cpp", "ca_kernels.hip", "ca_cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

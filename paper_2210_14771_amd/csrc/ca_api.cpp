@@ -11,7 +11,7 @@
 #include <new>
 #include <vector>
 
-#include "ca_internal.h"
+#include "ca_cnn.h"
 
 namespace {
 
@@ -128,6 +128,7 @@ struct ca_ctx {
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork = nullptr;
     hipEvent_t join[2] = {nullptr, nullptr};
+    uint8_t *model = nullptr;   // learned scorer, device block (ca_set_model)
 };
 
 namespace {
@@ -166,6 +167,8 @@ int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p)
     if (p.ransac_attempts < 1 || p.ransac_attempts > CA_MAX_ATTEMPTS)
         return CA_E_INVAL;
     if (p.refine_iters < 0 || p.refine_iters > 64 || (p.sampler != 0 && p.sampler != 1))
+        return CA_E_INVAL;
+    if (p.scorer != CA_SCORER_HANDCRAFTED && p.scorer != CA_SCORER_LEARNED)
         return CA_E_INVAL;
     if (!(p.t_g > 0) || !(p.t_theta_deg > 0) || !(p.t_iota > 0) || !(p.t_ri >= 0)
         || !std::isfinite(p.alpha) || !std::isfinite(p.t_ps) || !std::isfinite(p.t_cs)
@@ -363,7 +366,7 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     ra.r_max = p.r_max;
     ra.d_max = p.d_max;
     ra.t_ps = (float)p.t_ps;
-    ra.t_px = p.t_px;
+    ra.t_px = p.scorer == CA_SCORER_LEARNED ? 0 : p.t_px;  // Table A1: t_px is handcrafted only
     ra.P = pl->P;
     ra.attempts = p.ransac_attempts;
     ra.refine = p.refine_iters;
@@ -383,7 +386,7 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     hipEvent_t *ev = nullptr;
     if (timed && ctx->prof_used < ctx->prof_capacity)
         ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
-    if (ctx->schedule == CA_SCHEDULE_FUSED) {
+    if (ctx->schedule == CA_SCHEDULE_FUSED && p.scorer == CA_SCORER_HANDCRAFTED) {
         ca::FusedArgs fa;
         fa.s = sa;
         fa.r = ra;
@@ -404,6 +407,7 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     }
     // strips then RANSAC for frames [f0, f1) on stream st
     const int S = p.n_hstrips + p.n_vstrips;
+    const bool learned = p.scorer == CA_SCORER_LEARNED;
     auto launch_range = [&](int32_t f0, int32_t f1, hipStream_t st, hipEvent_t mid) {
         ca::StripArgs a2 = sa;
         a2.frame0 = f0;
@@ -411,8 +415,24 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
         a2.per_xcd = (a2.n_items + 7) / 8;
         ca::RansacArgs r2 = ra;
         r2.frame0 = f0;
-        return ca::launch_strips(a2, pl->lds, st) == hipSuccess
-               && (!mid || hipEventRecord(mid, st) == hipSuccess)
+        bool ok;
+        if (learned) {
+            ca::CnnStripArgs c;
+            c.frames = frames;
+            c.fd = pl->fd;
+            c.strips = pl->strips;
+            c.model = ctx->model;
+            c.cand = sa.cand;
+            c.n_h = p.n_hstrips;
+            c.n_v = p.n_vstrips;
+            c.n_items = a2.n_items;
+            c.per_xcd = a2.per_xcd;
+            c.frame0 = f0;
+            ok = ca::launch_cnn_strips(c, st) == hipSuccess;
+        } else {
+            ok = ca::launch_strips(a2, pl->lds, st) == hipSuccess;
+        }
+        return ok && (!mid || hipEventRecord(mid, st) == hipSuccess)
                && ca::launch_ransac(r2, se, f1 - f0, st) == hipSuccess;
     };
     const int32_t nsub = ctx->pipeline > 1 ? (int32_t)std::min<int64_t>(ctx->pipeline, n) : 1;
@@ -467,6 +487,8 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
     int rc = validate(dims, n, p);
     if (rc != CA_OK)
         return rc;
+    if (p.scorer == CA_SCORER_LEARNED && !ctx->model)
+        return CA_E_INVAL;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
         return CA_E_DEVICE;
@@ -512,6 +534,7 @@ void ca_default_params(ca_params *p)
     p->ransac_attempts = 256;
     p->sampler = 0;
     p->seed = 0;
+    p->scorer = CA_SCORER_HANDCRAFTED;
 }
 
 int ca_create(ca_ctx **out, int device, size_t budget)
@@ -587,6 +610,8 @@ void ca_destroy(ca_ctx *ctx)
         }
         if (ctx->fork)
             (void)hipEventDestroy(ctx->fork);
+        if (ctx->model)
+            (void)hipFree(ctx->model);
     }
     delete ctx;
 }
@@ -692,6 +717,8 @@ int ca_graph_create(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dim
         p = *params;
     else
         ca_default_params(&p);
+    if (p.scorer == CA_SCORER_LEARNED && !ctx->model)
+        return CA_E_INVAL;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
         return CA_E_DEVICE;
@@ -762,6 +789,107 @@ void ca_graph_destroy(ca_graph *g)
     }
     --g->plan->pins;
     delete g;
+}
+
+namespace {
+
+uint16_t to_bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t rounding = ((u >> 16) & 1u) + 0x7FFFu;  // round to nearest even
+    return (uint16_t)((u + rounding) >> 16);
+}
+
+float bf16_value(float f)
+{
+    const uint32_t u = (uint32_t)to_bf16_bits(f) << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
+// Model file (float32, W[out][in][tap] per layer) -> device block layout.
+void pack_model(const float *prm, std::vector<uint8_t> &out)
+{
+    out.assign(ca::kCnnModelBytes, 0);
+    uint16_t *w = reinterpret_cast<uint16_t *>(out.data());
+    float *fb = reinterpret_cast<float *>(out.data() + (size_t)ca::kCnnWElems * 2);
+    const int cin[4] = {24, 16, 32, 32}, cout[4] = {16, 32, 32, 16}, kp[4] = {128, 96, 160, 160};
+    size_t at = 0;
+    for (int l = 0; l < 4; ++l) {
+        for (int o = 0; o < cout[l]; ++o)
+            for (int c = 0; c < cin[l]; ++c)
+                for (int t = 0; t < 5; ++t)
+                    w[ca::kCnnWOff[l] + o * kp[l] + t * cin[l] + c] =
+                        to_bf16_bits(prm[at + ((size_t)o * cin[l] + c) * 5 + t]);
+        at += (size_t)cout[l] * cin[l] * 5;
+        for (int o = 0; o < cout[l]; ++o)
+            fb[ca::kCnnBOff[l] + o] = prm[at + o];
+        at += cout[l];
+    }
+    for (int c = 0; c < 16; ++c)
+        fb[ca::kCnnW5Off + c] = bf16_value(prm[at + c]);
+    at += 16;
+    fb[ca::kCnnW5Off + 16] = prm[at];
+}
+
+}  // namespace
+
+int ca_set_model(ca_ctx *ctx, const float *prm, int32_t n)
+{
+    if (!ctx || !prm || n != CA_CNN_PARAMS)
+        return CA_E_INVAL;
+    for (int32_t i = 0; i < n; ++i)
+        if (!std::isfinite(prm[i]))
+            return CA_E_INVAL;
+    std::vector<uint8_t> block;
+    try {
+        pack_model(prm, block);
+    } catch (...) {
+        return CA_E_NOMEM;
+    }
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (!ctx->model) {
+        if (hipMalloc(&ctx->model, ca::kCnnModelBytes) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->model = nullptr;
+            return CA_E_NOMEM;
+        }
+    }
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(ctx->model, block.data(), block.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_cnn_window_logits(ca_ctx *ctx, const uint8_t *win, const int32_t *range, int32_t n,
+                         float *z, void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!win || !range || !z)))
+        return CA_E_INVAL;
+    if (!ctx->model)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return ca::launch_cnn_windows(ctx->model, win, range, z, n, static_cast<hipStream_t>(stream))
+                   == hipSuccess
+               ? CA_OK
+               : CA_E_DEVICE;
+}
+
+int ca_selftest_mfma(ca_ctx *ctx, float *out, void *stream)
+{
+    if (!ctx || !out)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return ca::launch_mfma_probe(out, static_cast<hipStream_t>(stream)) == hipSuccess ? CA_OK
+                                                                                       : CA_E_DEVICE;
 }
 
 int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
