@@ -85,11 +85,15 @@ typedef struct {
     uint64_t seed;           /* key of the counter-based sampler */
     int32_t scorer;          /* CA_SCORER_HANDCRAFTED (Section 2.2.3) or CA_SCORER_LEARNED
                                 (Section 2.2.4; needs ca_set_model; t_px is not applied) */
-    int32_t reserved;
+    float fallback_inlier_frac; /* learned scorer only: a frame whose best circle has
+                                   inliers < fallback_inlier_frac * n_points (or fewer than
+                                   3 kept points) takes the handcrafted pipeline's result
+                                   instead; 0 (default) = no fallback; [0, 1] */
 } ca_params;
 
 #define CA_SCORER_HANDCRAFTED 0
 #define CA_SCORER_LEARNED 1
+#define CA_REASON_FALLBACK 256
 
 /* Result per frame (32 bytes). */
 typedef struct {
@@ -99,7 +103,9 @@ typedef struct {
     int32_t n_points;        /* candidate points kept after filtering */
     int32_t valid;           /* 1: content area = disc within the frame; 0: whole frame */
     int32_t reason;          /* 0 valid, 1 fewer than 3 points, 2 no attempt within the
-                                radius and centre limits, 3 best score below t_cs */
+                                radius and centre limits, 3 best score below t_cs;
+                                + CA_REASON_FALLBACK when the learned scorer's result
+                                was replaced by the handcrafted one */
 } ca_result;
 
 /* Best pixel of one half strip (8 bytes).  Frame f's P candidates are
@@ -176,8 +182,47 @@ int ca_debug_attempts(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_des
 #define CA_CNN_WINDOW 128      /* positions per window */
 #define CA_CNN_OUTPUTS 112     /* exact logits per window: positions 8 .. 119 */
 
-/* Load (host pointer) the model used by scorer CA_SCORER_LEARNED.  Blocking. */
+/* Load (host pointer) the model used by scorer CA_SCORER_LEARNED.  The values
+ * become the context's float32 master weights (training starts from them
+ * with zero momentum); the device model holds their bfloat16 roundings.
+ * Blocking.  CA_E_INVAL for a wrong count or a non-finite value. */
 int ca_set_model(ca_ctx *ctx, const float *params_host, int32_t n_params);
+
+/* Copy the master weights and, when `momentum_host` is not NULL, the SGD
+ * momentum (CA_CNN_PARAMS floats each, model-file order) to the host.
+ * Blocking.  CA_E_INVAL without a model. */
+int ca_get_model(ca_ctx *ctx, float *params_host, float *momentum_host, int32_t n_params);
+
+/* Replace the SGD momentum (host array, model-file order), e.g. to resume
+ * training from a checkpoint taken with ca_get_model.  Blocking. */
+int ca_set_momentum(ca_ctx *ctx, const float *momentum_host, int32_t n_params);
+
+/* Training (Section 2.2.4: soft binary cross entropy against blurred edge
+ * labels, SGD).  Gradients, with respect to the master weights, of
+ *   L = scale * sum_i sum_j weight[i][j] * BCE(sigmoid(z_ij), target[i][j])
+ * over n windows of the current model, z_ij the logit of central position
+ * 8 + j of window i (the forward pass of ca_cnn_window_logits).  The
+ * backward pass stores its signals in bfloat16 and sums in float32; each
+ * hidden unit's ReLU passes the gradient where its stored activation is > 0.
+ *   windows_dev  uint8 [n][8][CA_CNN_WINDOW][3], as for ca_cnn_window_logits
+ *   range_dev    int32 [n][2], as for ca_cnn_window_logits; central
+ *                positions outside [lo, hi) carry no loss
+ *   target_dev   float [n][CA_CNN_OUTPUTS], soft labels in [0, 1]
+ *   weight_dev   float [n][CA_CNN_OUTPUTS], >= 0
+ *   grad_dev     float [CA_CNN_PARAMS], written in model-file order
+ *   loss_dev     float [1], the value of L
+ * Enqueued on `stream` (device pointers, asynchronous).  The context's
+ * gradient workspace is shared by its calls: calls that overlap on
+ * different streams race.  n = 0 writes zeros.  Needs ca_set_model. */
+int ca_cnn_gradients(ca_ctx *ctx, const uint8_t *windows_dev, const int32_t *range_dev,
+                     const float *target_dev, const float *weight_dev, int32_t n_windows,
+                     float scale, float *grad_dev, float *loss_dev, void *stream);
+
+/* One SGD step with momentum on the master weights, m = mu m + g,
+ * p = p - lr m (g: device array of CA_CNN_PARAMS floats in model-file
+ * order), then the device model is rebuilt from p.  Enqueued on `stream`. */
+int ca_cnn_sgd_step(ca_ctx *ctx, const float *grad_dev, float lr, float momentum,
+                    void *stream);
 
 /* Logits of windows (for tests and training data checks): `windows_dev` is
  * uint8 [n][8][CA_CNN_WINDOW][3] (line, position, colour); `range_dev` is

@@ -18,7 +18,11 @@ Numeric definition (shared with the GPU kernels by definition, not by code):
   * logit z, score sigmoid(z).
 The oracle evaluates every sum in float64; only the storage roundings are
 emulated.  Gradients follow the chain rule through the stored values
-(rounding is treated as identity), the loss being the mean soft BCE.
+(rounding is treated as identity), the loss being the mean soft BCE.  With
+``grad_bf16`` the backward signal at each hidden pre-activation (ReLU mask
+applied) is also stored in bfloat16, as a training pass that keeps its
+backward activations in bfloat16 does; the 1x1 layer's logit gradient stays
+exact.
 """
 from __future__ import annotations
 
@@ -124,7 +128,7 @@ def conv_backward(x: np.ndarray, w: np.ndarray, dy: np.ndarray):
     return dxp[:, half:half + L], dw, db
 
 
-def backward(cache: dict, params, dz: np.ndarray, mask=None):
+def backward(cache: dict, params, dz: np.ndarray, mask=None, grad_bf16: bool = False):
     """Parameter gradients for an upstream gradient dz on the logits."""
     h = cache["h"]
     grads = [None] * len(params)
@@ -136,6 +140,8 @@ def backward(cache: dict, params, dz: np.ndarray, mask=None):
         dpre = dx * (cache["pre"][li] > 0)
         if mask is not None:
             dpre = np.where(mask[None, :], dpre, 0.0)
+        if grad_bf16:
+            dpre = bf16(dpre)
         dx, dw, db = conv_backward(h[li], w, dpre)
         grads[li] = (dw, db)
     return grads
@@ -173,15 +179,18 @@ def window_forward(win_u8: np.ndarray, lo: int, hi: int, params) -> np.ndarray:
     return np.where(mask[HALO:WINDOW - HALO], z, np.nan)
 
 
-def loss_and_grads(xs, ts, params, store_bf16: bool = True, masks=None, weights=None):
-    """Mean soft-BCE over all weighted positions of a list of strips, and its
-    gradients.  `weights` (optional, per strip, per position, 0/1) selects the
-    positions that carry a loss; `masks` marks positions inside the strip."""
+def loss_and_grads(xs, ts, params, store_bf16: bool = True, masks=None, weights=None,
+                   scale=None, grad_bf16: bool = False):
+    """Weighted soft-BCE over the positions of a list of strips, and its
+    gradients: scale * sum of weight * BCE, scale = 1 / (sum of the weights)
+    unless given (the mean when every weight is 1).  `weights` (optional, per
+    strip, per position, >= 0) selects the positions that carry a loss;
+    `masks` marks positions inside the strip."""
     if weights is None:
         weights = [np.ones(len(t)) for t in ts]
     if masks is None:
         masks = [None] * len(ts)
-    total = sum(float(w.sum()) for w in weights)
+    total = sum(float(w.sum()) for w in weights) if scale is None else 1.0 / scale
     loss = 0.0
     acc = [(np.zeros_like(w), np.zeros_like(b)) for w, b in params]
     for x, t, m, wt in zip(xs, ts, masks, weights):
@@ -190,7 +199,7 @@ def loss_and_grads(xs, ts, params, store_bf16: bool = True, masks=None, weights=
         s = c["s"]
         loss += float(np.sum(-wt * (t * np.log(s + eps) + (1 - t) * np.log(1 - s + eps)))) / total
         dz = wt * (s - t) / total
-        g = backward(c, params, dz, m)
+        g = backward(c, params, dz, m, grad_bf16)
         acc = [(a[0] + gw, a[1] + gb) for a, (gw, gb) in zip(acc, g)]
     return loss, acc
 

@@ -25,10 +25,12 @@ EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_debug_candidates", "ca_debug_attempts", "ca_check_args", "ca_strip_positions",
            "ca_score_tables", "ca_profile_begin", "ca_profile_end", "ca_set_option",
            "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
-           "ca_graph_destroy", "ca_set_model", "ca_cnn_window_logits", "ca_selftest_mfma",
+           "ca_graph_destroy", "ca_set_model", "ca_get_model", "ca_set_momentum",
+           "ca_cnn_window_logits", "ca_cnn_gradients", "ca_cnn_sgd_step", "ca_selftest_mfma",
            "ca_error_string", "ca_version")
 CA_SCORER_HANDCRAFTED = 0
 CA_SCORER_LEARNED = 1
+CA_REASON_FALLBACK = 256
 CA_CNN_PARAMS = 12273
 CA_CNN_WINDOW = 128
 CA_CNN_OUTPUTS = 112
@@ -55,7 +57,7 @@ class Params(C.Structure):
                 ("refine_iters", C.c_int32), ("t_ri", C.c_double), ("r_min", C.c_double),
                 ("r_max", C.c_double), ("d_max", C.c_double), ("ransac_attempts", C.c_int32),
                 ("sampler", C.c_int32), ("seed", C.c_uint64), ("scorer", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("fallback_inlier_frac", C.c_float)]
 
 
 class ResultRec(C.Structure):
@@ -120,7 +122,11 @@ def lib() -> C.CDLL:
         L.ca_graph_destroy.argtypes = [vp]
         L.ca_graph_destroy.restype = None
         L.ca_set_model.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.ca_get_model.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), i32]
+        L.ca_set_momentum.argtypes = [vp, C.POINTER(C.c_float), i32]
         L.ca_cnn_window_logits.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.ca_cnn_gradients.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
+        L.ca_cnn_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
         L.ca_selftest_mfma.argtypes = [vp, vp, vp]
         L.ca_set_option.argtypes = [vp, i32, C.c_int64]
         L.ca_get_option.argtypes = [vp, i32, C.POINTER(C.c_int64)]

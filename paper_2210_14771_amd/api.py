@@ -224,6 +224,57 @@ class Estimator:
                 "ca_cnn_window_logits")
         return z
 
+    def get_model(self, with_momentum: bool = False):
+        """Master weights (and the SGD momentum) as float32 numpy arrays."""
+        import numpy as np
+        prm = np.empty(N.CA_CNN_PARAMS, dtype=np.float32)
+        mom = np.empty(N.CA_CNN_PARAMS, dtype=np.float32) if with_momentum else None
+        fp = C.POINTER(C.c_float)
+        N.check(N.lib().ca_get_model(self._ctx, prm.ctypes.data_as(fp),
+                                     mom.ctypes.data_as(fp) if mom is not None else None,
+                                     prm.size), "ca_get_model")
+        return (prm, mom) if with_momentum else prm
+
+    def set_momentum(self, momentum) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(momentum, dtype=np.float32).ravel()
+        N.check(N.lib().ca_set_momentum(self._ctx, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+                "ca_set_momentum")
+
+    def cnn_gradients(self, windows: torch.Tensor, ranges: torch.Tensor, targets: torch.Tensor,
+                      weights: torch.Tensor, scale: float, stream=None):
+        """(grad [CA_CNN_PARAMS], loss [1]) device tensors of the weighted soft BCE."""
+        if windows.dtype != torch.uint8 or tuple(windows.shape[1:]) != (8, N.CA_CNN_WINDOW, 3):
+            raise ValueError("windows must be uint8 [n, 8, 128, 3]")
+        n = windows.shape[0]
+        for t, name in ((targets, "targets"), (weights, "weights")):
+            if t.dtype != torch.float32 or tuple(t.shape) != (n, N.CA_CNN_OUTPUTS):
+                raise ValueError(f"{name} must be float32 [n, {N.CA_CNN_OUTPUTS}]")
+        if tuple(ranges.shape) != (n, 2):
+            raise ValueError("ranges must be [n, 2]")
+        windows = windows.contiguous()
+        ranges = ranges.to(torch.int32).contiguous()
+        targets = targets.contiguous()
+        weights = weights.contiguous()
+        grad = torch.empty(N.CA_CNN_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        vp = C.c_void_p
+        N.check(N.lib().ca_cnn_gradients(self._ctx, vp(windows.data_ptr()), vp(ranges.data_ptr()),
+                                         vp(targets.data_ptr()), vp(weights.data_ptr()), n,
+                                         float(scale), vp(grad.data_ptr()), vp(loss.data_ptr()),
+                                         vp(s.cuda_stream)), "ca_cnn_gradients")
+        return grad, loss
+
+    def cnn_sgd_step(self, grad: torch.Tensor, lr: float, momentum: float, stream=None) -> None:
+        """m = momentum m + grad; p -= lr m on the master weights; rebuild the model."""
+        if grad.dtype != torch.float32 or grad.numel() != N.CA_CNN_PARAMS or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous float32 tensor of CA_CNN_PARAMS values")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        N.check(N.lib().ca_cnn_sgd_step(self._ctx, C.c_void_p(grad.data_ptr()), float(lr),
+                                        float(momentum), C.c_void_p(s.cuda_stream)),
+                "ca_cnn_sgd_step")
+
     def selftest_mfma(self) -> torch.Tensor:
         out = torch.empty((16, 16), dtype=torch.float32, device=self.device)
         s = torch.cuda.current_stream(self.device)

@@ -12,6 +12,9 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB_PATH = os.path.join(OUT_DIR, "libcontentarea.so")
 SOURCES = ["ca_api.cpp", "ca_kernels.hip", "ca_cnn.hip"]
+# the device renderer of synthetic frames: an input generator, built apart
+SYNTH_LIB_PATH = os.path.join(OUT_DIR, "libcasynth.so")
+SYNTH_SOURCES = ["synth_gpu.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -30,18 +33,23 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libcontentarea.so; returns its path."""
-    os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB_PATH + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", INCLUDE, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _link(sources, path, verbose):
+    tmp = path + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-I", INCLUDE, *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed to build libcontentarea.so")
-    os.replace(tmp, LIB_PATH)
+        raise RuntimeError(f"hipcc failed to build {os.path.basename(path)}")
+    os.replace(tmp, path)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libcontentarea.so and libcasynth.so; returns the former's path."""
+    os.makedirs(OUT_DIR, exist_ok=True)
+    _link(SOURCES, LIB_PATH, verbose)
+    _link(SYNTH_SOURCES, SYNTH_LIB_PATH, verbose)
     return LIB_PATH
 
 

@@ -83,6 +83,7 @@ struct Plan {
     ca_point *cand = nullptr;
     Record *rec = nullptr;
     uint32_t *ctl = nullptr;    // fused-kernel control words (zero between calls)
+    ca_result *res2 = nullptr;  // handcrafted results of a learned call with fallback
     // launch facts
     int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
     bool rows_aligned = false;  // every row offset a multiple of 16
@@ -129,6 +130,9 @@ struct ca_ctx {
     hipEvent_t fork = nullptr;
     hipEvent_t join[2] = {nullptr, nullptr};
     uint8_t *model = nullptr;   // learned scorer, device block (ca_set_model)
+    float *train = nullptr;     // master weights [kCnnParams], then momentum [kCnnParams]
+    float *partial = nullptr;   // gradient partials [grad_grid][kCnnGradStride]
+    int grad_grid = 0;
 };
 
 namespace {
@@ -169,6 +173,8 @@ int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p)
     if (p.refine_iters < 0 || p.refine_iters > 64 || (p.sampler != 0 && p.sampler != 1))
         return CA_E_INVAL;
     if (p.scorer != CA_SCORER_HANDCRAFTED && p.scorer != CA_SCORER_LEARNED)
+        return CA_E_INVAL;
+    if (!(p.fallback_inlier_frac >= 0.0f && p.fallback_inlier_frac <= 1.0f))
         return CA_E_INVAL;
     if (!(p.t_g > 0) || !(p.t_theta_deg > 0) || !(p.t_iota > 0) || !(p.t_ri >= 0)
         || !std::isfinite(p.alpha) || !std::isfinite(p.t_ps) || !std::isfinite(p.t_cs)
@@ -259,7 +265,8 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     const size_t o_cand = align_up(o_lut + sizeof(float) * lut.size(), 256);
     const size_t o_rec = align_up(o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
     const size_t o_ctl = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
-    const size_t total = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
+    const size_t o_res2 = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
+    const size_t total = align_up(o_res2 + sizeof(ca_result) * (size_t)n, 256);
 
     // evict least recently used unpinned plans until this one fits the budget
     while (ctx->used + total > ctx->budget) {
@@ -291,6 +298,7 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     pl->cand = reinterpret_cast<ca_point *>(base + o_cand);
     pl->rec = reinterpret_cast<Record *>(base + o_rec);
     pl->ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
+    pl->res2 = reinterpret_cast<ca_result *>(base + o_res2);
     // plans are built once per batch shape; a blocking upload keeps them simple
     bool ok = hipMemcpy(pl->fd, fd.data(), sizeof(FrameDev) * (size_t)n, hipMemcpyHostToDevice)
                   == hipSuccess
@@ -335,9 +343,9 @@ int get_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params 
 }
 
 // Enqueue the whole path for one batch on stream `s`.
-int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
-            ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
-            bool timed)
+int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
+                ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
+                bool timed)
 {
 
     ca::StripArgs sa;
@@ -467,6 +475,27 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
                || hipEventRecord(ev[3], s) != hipSuccess))
         return CA_E_DEVICE;
     return CA_OK;
+}
+
+// One call: the learned scorer's pipeline, then, with a fallback fraction,
+// the handcrafted pipeline into the plan's second result array and a
+// per-frame choice between the two.
+int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
+            ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
+            bool timed)
+{
+    int rc = enqueue_one(ctx, pl, frames, n, p, points_out, attempts_out, out, s, timed);
+    if (rc != CA_OK || p.scorer != CA_SCORER_LEARNED || !(p.fallback_inlier_frac > 0.0f))
+        return rc;
+    ca_params h = p;
+    h.scorer = CA_SCORER_HANDCRAFTED;
+    h.fallback_inlier_frac = 0.0f;
+    rc = enqueue_one(ctx, pl, frames, n, h, nullptr, nullptr, pl->res2, s, false);
+    if (rc != CA_OK)
+        return rc;
+    return ca::launch_fallback(out, pl->res2, n, p.fallback_inlier_frac, s) == hipSuccess
+               ? CA_OK
+               : CA_E_DEVICE;
 }
 
 int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
@@ -612,6 +641,10 @@ void ca_destroy(ca_ctx *ctx)
             (void)hipEventDestroy(ctx->fork);
         if (ctx->model)
             (void)hipFree(ctx->model);
+        if (ctx->train)
+            (void)hipFree(ctx->train);
+        if (ctx->partial)
+            (void)hipFree(ctx->partial);
     }
     delete ctx;
 }
@@ -793,62 +826,22 @@ void ca_graph_destroy(ca_graph *g)
 
 namespace {
 
-uint16_t to_bf16_bits(float f)
-{
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    const uint32_t rounding = ((u >> 16) & 1u) + 0x7FFFu;  // round to nearest even
-    return (uint16_t)((u + rounding) >> 16);
-}
+constexpr size_t kTrainFloats = 2 * (size_t)CA_CNN_PARAMS;
 
-float bf16_value(float f)
+bool finite_all(const float *v, int32_t n)
 {
-    const uint32_t u = (uint32_t)to_bf16_bits(f) << 16;
-    float v;
-    std::memcpy(&v, &u, 4);
-    return v;
-}
-
-// Model file (float32, W[out][in][tap] per layer) -> device block layout.
-void pack_model(const float *prm, std::vector<uint8_t> &out)
-{
-    out.assign(ca::kCnnModelBytes, 0);
-    uint16_t *w = reinterpret_cast<uint16_t *>(out.data());
-    float *fb = reinterpret_cast<float *>(out.data() + (size_t)ca::kCnnWElems * 2);
-    const int cin[4] = {24, 16, 32, 32}, cout[4] = {16, 32, 32, 16}, kp[4] = {128, 96, 160, 160};
-    size_t at = 0;
-    for (int l = 0; l < 4; ++l) {
-        for (int o = 0; o < cout[l]; ++o)
-            for (int c = 0; c < cin[l]; ++c)
-                for (int t = 0; t < 5; ++t)
-                    w[ca::kCnnWOff[l] + o * kp[l] + t * cin[l] + c] =
-                        to_bf16_bits(prm[at + ((size_t)o * cin[l] + c) * 5 + t]);
-        at += (size_t)cout[l] * cin[l] * 5;
-        for (int o = 0; o < cout[l]; ++o)
-            fb[ca::kCnnBOff[l] + o] = prm[at + o];
-        at += cout[l];
-    }
-    for (int c = 0; c < 16; ++c)
-        fb[ca::kCnnW5Off + c] = bf16_value(prm[at + c]);
-    at += 16;
-    fb[ca::kCnnW5Off + 16] = prm[at];
+    for (int32_t i = 0; i < n; ++i)
+        if (!std::isfinite(v[i]))
+            return false;
+    return true;
 }
 
 }  // namespace
 
 int ca_set_model(ca_ctx *ctx, const float *prm, int32_t n)
 {
-    if (!ctx || !prm || n != CA_CNN_PARAMS)
+    if (!ctx || !prm || n != CA_CNN_PARAMS || !finite_all(prm, n))
         return CA_E_INVAL;
-    for (int32_t i = 0; i < n; ++i)
-        if (!std::isfinite(prm[i]))
-            return CA_E_INVAL;
-    std::vector<uint8_t> block;
-    try {
-        pack_model(prm, block);
-    } catch (...) {
-        return CA_E_NOMEM;
-    }
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
         return CA_E_DEVICE;
@@ -859,10 +852,107 @@ int ca_set_model(ca_ctx *ctx, const float *prm, int32_t n)
             return CA_E_NOMEM;
         }
     }
+    if (!ctx->train) {
+        if (hipMalloc(&ctx->train, kTrainFloats * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->train = nullptr;
+            return CA_E_NOMEM;
+        }
+    }
     if (hipDeviceSynchronize() != hipSuccess
-        || hipMemcpy(ctx->model, block.data(), block.size(), hipMemcpyHostToDevice) != hipSuccess)
+        || hipMemcpy(ctx->train, prm, (size_t)n * sizeof(float), hipMemcpyHostToDevice)
+               != hipSuccess
+        || hipMemset(ctx->train + CA_CNN_PARAMS, 0, (size_t)n * sizeof(float)) != hipSuccess
+        || ca::launch_cnn_pack(ctx->train, ctx->model, nullptr) != hipSuccess
+        || hipDeviceSynchronize() != hipSuccess)
         return CA_E_DEVICE;
     return CA_OK;
+}
+
+int ca_get_model(ca_ctx *ctx, float *prm, float *mom, int32_t n)
+{
+    if (!ctx || !prm || n != CA_CNN_PARAMS || !ctx->train)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(prm, ctx->train, (size_t)n * sizeof(float), hipMemcpyDeviceToHost)
+               != hipSuccess)
+        return CA_E_DEVICE;
+    if (mom && hipMemcpy(mom, ctx->train + CA_CNN_PARAMS, (size_t)n * sizeof(float),
+                         hipMemcpyDeviceToHost) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_set_momentum(ca_ctx *ctx, const float *mom, int32_t n)
+{
+    if (!ctx || !mom || n != CA_CNN_PARAMS || !ctx->train || !finite_all(mom, n))
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(ctx->train + CA_CNN_PARAMS, mom, (size_t)n * sizeof(float),
+                     hipMemcpyHostToDevice) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_cnn_gradients(ca_ctx *ctx, const uint8_t *win, const int32_t *range, const float *target,
+                     const float *weight, int32_t n, float scale, float *grad, float *loss,
+                     void *stream)
+{
+    if (!ctx || n < 0 || !grad || !loss || !std::isfinite(scale)
+        || (n > 0 && (!win || !range || !target || !weight)))
+        return CA_E_INVAL;
+    if (!ctx->model)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (!ctx->partial) {
+        // two resident workgroups per compute unit (LDS and registers allow two)
+        const int grid = 2 * (ctx->n_cu > 0 ? ctx->n_cu : 256);
+        if (hipMalloc(&ctx->partial, (size_t)grid * ca::kCnnGradStride * sizeof(float))
+            != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->partial = nullptr;
+            return CA_E_NOMEM;
+        }
+        ctx->grad_grid = grid;
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = n < ctx->grad_grid ? (n > 0 ? n : 1) : ctx->grad_grid;
+    ca::CnnTrainArgs a;
+    a.model = ctx->model;
+    a.win = win;
+    a.range = range;
+    a.target = target;
+    a.weight = weight;
+    a.partial = ctx->partial;
+    a.scale = scale;
+    a.n = n;
+    if (ca::launch_cnn_grad(a, grid, st) != hipSuccess
+        || ca::launch_cnn_reduce(ctx->partial, grid, grad, loss, st) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_cnn_sgd_step(ca_ctx *ctx, const float *grad, float lr, float mu, void *stream)
+{
+    if (!ctx || !grad || !std::isfinite(lr) || !std::isfinite(mu))
+        return CA_E_INVAL;
+    if (!ctx->train)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return ca::launch_cnn_update(ctx->train, ctx->train + CA_CNN_PARAMS, grad, lr, mu, ctx->model,
+                                 static_cast<hipStream_t>(stream)) == hipSuccess
+               ? CA_OK
+               : CA_E_DEVICE;
 }
 
 int ca_cnn_window_logits(ca_ctx *ctx, const uint8_t *win, const int32_t *range, int32_t n,

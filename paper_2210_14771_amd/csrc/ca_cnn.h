@@ -22,8 +22,17 @@ constexpr int kCnnWElems = 16 * 128 + 32 * 96 + 32 * 160 + 16 * 160;   // 12800
 constexpr int kCnnBOff[4] = {0, 16, 48, 80};
 constexpr int kCnnW5Off = 96;                                           // w5[16], then b5
 constexpr int kCnnFloats = 96 + 16 + 1;
-constexpr size_t kCnnModelBytes = (size_t)kCnnWElems * 2 + 128 * sizeof(float);
+// Flipped weights for the input gradients of layers 2-4:
+// Wf_l[c][t' C_out + o] = W_l[o][(4 - t') C_in + c], K' padded to 32.
+constexpr int kCnnFOff[3] = {0, 16 * 160, 16 * 160 + 32 * 160};       // layers 2, 3, 4
+constexpr int kCnnFElems = 16 * 160 + 32 * 160 + 32 * 96;              // 10752
+constexpr size_t kCnnFloatsOff = (size_t)kCnnWElems * 2;               // byte offset
+constexpr size_t kCnnFlipOff = kCnnFloatsOff + 128 * sizeof(float);    // byte offset
+constexpr size_t kCnnModelBytes = kCnnFlipOff + (size_t)kCnnFElems * 2;
 constexpr int kCnnParams = 12273;   // float32 parameters of the model file
+// Gradient accumulators in GEMM layout: W1..W4 as kCnnWElems floats, then
+// biases of layers 1-4 (96), w5 (16), b5, the loss: kCnnGradStride floats.
+constexpr int kCnnGradStride = kCnnWElems + 128;
 
 struct __attribute__((aligned(16))) CnnLds {
     __bf16 w[kCnnWElems];
@@ -47,6 +56,28 @@ struct CnnStripArgs {
     int32_t per_xcd;
     int32_t frame0;
 };
+
+struct CnnTrainArgs {
+    const uint8_t *model;     // device model block (weights read from global memory)
+    const uint8_t *win;       // [n][8][128][3]
+    const int32_t *range;     // [n][2]
+    const float *target;      // [n][112]
+    const float *weight;      // [n][112] loss weight per output position
+    float *partial;           // [grid][kCnnGradStride]
+    float scale;              // multiplies every position's loss term
+    int32_t n;
+};
+
+hipError_t launch_cnn_grad(const CnnTrainArgs &a, int grid, hipStream_t s);
+// Sum `grid` partials, then (file order) grad_out[i] and loss_out[0].
+hipError_t launch_cnn_reduce(const float *partial, int grid, float *grad_out, float *loss_out,
+                             hipStream_t s);
+// SGD with momentum on the float32 master weights (file order), then repack
+// the device model block.
+hipError_t launch_cnn_update(float *master, float *momentum, const float *grad, float lr,
+                             float mom, uint8_t *model, hipStream_t s);
+// Repack the device model block from master weights.
+hipError_t launch_cnn_pack(const float *master, uint8_t *model, hipStream_t s);
 
 hipError_t launch_mfma_probe(float *out, hipStream_t s);
 hipError_t launch_cnn_windows(const uint8_t *model, const uint8_t *win, const int32_t *range,

@@ -81,27 +81,58 @@ __device__ void conv_forward(const __bf16 *W, const float *bias, const __bf16 *X
 }
 
 // Logits of all 128 window positions into z (valid for the central 112).
-__device__ void window_forward(CnnLds &s, int lo, int hi)
+// Weights w (GEMM layout) may live in LDS or in global memory.
+__device__ void window_forward(const __bf16 *w, const float *fb, const __bf16 *x0, __bf16 *h1,
+                               __bf16 *h2, __bf16 *h3, __bf16 *h4, float *zo, int lo, int hi)
 {
-    const __bf16 *w = s.w;
-    conv_forward<24, 16, 128>(w + kCnnWOff[0], s.fb + kCnnBOff[0], s.x0, s.h1, lo, hi);
+    conv_forward<24, 16, 128>(w + kCnnWOff[0], fb + kCnnBOff[0], x0, h1, lo, hi);
     __syncthreads();
-    conv_forward<16, 32, 96>(w + kCnnWOff[1], s.fb + kCnnBOff[1], s.h1, s.h2, lo, hi);
+    conv_forward<16, 32, 96>(w + kCnnWOff[1], fb + kCnnBOff[1], h1, h2, lo, hi);
     __syncthreads();
-    conv_forward<32, 32, 160>(w + kCnnWOff[2], s.fb + kCnnBOff[2], s.h2, s.h3, lo, hi);
+    conv_forward<32, 32, 160>(w + kCnnWOff[2], fb + kCnnBOff[2], h2, h3, lo, hi);
     __syncthreads();
-    conv_forward<32, 16, 160>(w + kCnnWOff[3], s.fb + kCnnBOff[3], s.h3, s.h4, lo, hi);
+    conv_forward<32, 16, 160>(w + kCnnWOff[3], fb + kCnnBOff[3], h3, h4, lo, hi);
     __syncthreads();
     const int n = threadIdx.x;
     if (n < kCnnWin) {
-        const __bf16 *h = s.h4 + (n + kCnnGuard) * 16;
-        float z = s.fb[kCnnW5Off + 16];
+        const __bf16 *h = h4 + (n + kCnnGuard) * 16;
+        float z = fb[kCnnW5Off + 16];
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-            z = fmaf(s.fb[kCnnW5Off + c], (float)h[c], z);
-        s.z[n] = z;
+            z = fmaf(fb[kCnnW5Off + c], (float)h[c], z);
+        zo[n] = z;
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ void window_forward(CnnLds &s, int lo, int hi)
+{
+    window_forward(s.w, s.fb, s.x0, s.h1, s.h2, s.h3, s.h4, s.z, lo, hi);
+}
+
+// One uint8 window [8][128][3] into the position-major input buffer,
+// zero outside [lo, hi).
+__device__ void load_window(__bf16 *x0, const uint8_t *src, int lo, int hi)
+{
+    for (int i = threadIdx.x; i < kCnnLines * kCnnWin * 3; i += kBlock) {
+        const int line = i / (kCnnWin * 3);
+        const int rem = i - line * (kCnnWin * 3);
+        const int n = rem / 3, ch = rem - 3 * (rem / 3);
+        const float v = (n >= lo && n < hi) ? ((float)src[i] - 128.0f) * (1.0f / 64.0f) : 0.0f;
+        x0[(n + kCnnGuard) * 24 + 3 * line + ch] = to_bf16(v);
+    }
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Clear the guard rows 0..G-1 and W+G..W+2G-1 of a position-major buffer.
+__device__ void zero_guards(__bf16 *buf, int chans)
+{
+    for (int i = threadIdx.x; i < 2 * kCnnGuard * chans; i += kBlock) {
+        const int row = i / chans;
+        const int r = row < kCnnGuard ? row : kCnnWin + row;
+        buf[r * chans + i % chans] = to_bf16(0.0f);
+    }
 }
 
 // Copy the model into LDS and clear the guard rows of the activation buffers.
@@ -115,14 +146,11 @@ __device__ void load_model(CnnLds &s, const uint8_t *model)
     const float *fsrc = reinterpret_cast<const float *>(model + kCnnWElems * 2);
     for (int i = threadIdx.x; i < kCnnFloats; i += kBlock)
         s.fb[i] = fsrc[i];
-    __bf16 *bufs[5] = {s.x0, s.h1, s.h2, s.h3, s.h4};
-    const int chans[5] = {24, 16, 32, 32, 16};
-    for (int b = 0; b < 5; ++b)
-        for (int i = threadIdx.x; i < 2 * kCnnGuard * chans[b]; i += kBlock) {
-            const int row = i / chans[b];
-            const int r = row < kCnnGuard ? row : kCnnWin + row;  // rows 0..G-1 and W+G..W+2G-1
-            bufs[b][r * chans[b] + i % chans[b]] = to_bf16(0.0f);
-        }
+    zero_guards(s.x0, 24);
+    zero_guards(s.h1, 16);
+    zero_guards(s.h2, 32);
+    zero_guards(s.h3, 32);
+    zero_guards(s.h4, 16);
 }
 
 // --------------------------------------------------------------- kernels --
@@ -158,14 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_cnn_windows(const uint8_t *model, co
     for (int wi = blockIdx.x; wi < n_windows; wi += gridDim.x) {
         const int lo = uniform_int(range[2 * wi]);
         const int hi = uniform_int(range[2 * wi + 1]);
-        const uint8_t *src = win + (int64_t)wi * (kCnnLines * kCnnWin * 3);
-        for (int i = threadIdx.x; i < kCnnLines * kCnnWin * 3; i += kBlock) {
-            const int line = i / (kCnnWin * 3);
-            const int rem = i - line * (kCnnWin * 3);
-            const int n = rem / 3, ch = rem - 3 * (rem / 3);
-            const float v = (n >= lo && n < hi) ? ((float)src[i] - 128.0f) * (1.0f / 64.0f) : 0.0f;
-            s.x0[(n + kCnnGuard) * 24 + 3 * line + ch] = to_bf16(v);
-        }
+        load_window(s.x0, win + (int64_t)wi * (kCnnLines * kCnnWin * 3), lo, hi);
         __syncthreads();
         window_forward(s, lo, hi);
         const int t = threadIdx.x;
@@ -229,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_cnn_strips(CnnStripArgs a)
         if (tid < kCnnOut) {
             const int p = p0 + tid;
             if (p < L) {
-                const float sc = 1.0f / (1.0f + __expf(-s.z[tid + kCnnHalo]));
+                const float sc = sigmoid(s.z[tid + kCnnHalo]);
                 const int half = p < (L >> 1) ? 0 : 1;
                 const int k = half == 0 ? p : L - 1 - p;
                 const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
@@ -267,6 +288,379 @@ __global__ __launch_bounds__(kBlock) void k_cnn_strips(CnnStripArgs a)
     }
 }
 
+// ------------------------------------------------------------- training --
+//
+// Backward pass of one window, given the forward activations (bfloat16) of
+// the same window.  Backward signals dP_l (the gradient at layer l's
+// pre-activation, ReLU mask applied) are stored in bfloat16, sums are float32
+// MFMA accumulators.  Only the central 112 logits carry a loss; every
+// activation they depend on is exact within the window, so the window's
+// gradients equal those of the whole strip restricted to those positions.
+//
+//   input gradients   dX_{l-1} = flipped-weight convolution of dP_l (a
+//                     forward-shaped GEMM), masked by h_{l-1} > 0;
+//   weight gradients  dW_l[o][t C_in + c] = sum_n dP_l[n][o] X[n + t - 2][c],
+//                     an MFMA GEMM whose reduction runs over the 128
+//                     positions; the tiles stay in registers across all the
+//                     windows of a workgroup;
+//   bias gradients    per-thread sums of dP_l, reduced at the end.
+
+struct __attribute__((aligned(16))) CnnGradLds {
+    float fb[128];
+    __bf16 x0[kCnnRows * 24];
+    __bf16 h1[kCnnRows * 16];
+    __bf16 h2[kCnnRows * 32];
+    __bf16 h3[kCnnRows * 32];   // later dP2, position-major
+    __bf16 h4[kCnnRows * 16];   // later dP4, position-major
+    __bf16 d32[kCnnRows * 32];  // dP3, position-major
+    __bf16 t[2][32 * kCnnWin];  // channel-major dP of two consecutive layers
+    float z[kCnnWin];           // logits, then dL/dz
+};
+
+// Input gradient of one layer: Dout/Tout[n][c] = [h(n, c) > 0] * sum_k'
+// Wf[c][k'] D[(n + G - 2) CI + k'], zero outside [lo, hi).  CI = channels of
+// dP (the layer's outputs), CO = the layer's inputs.
+template <int CI, int CO, int KP>
+__device__ void input_grad(const __bf16 *Wf, const __bf16 *D, const __bf16 *Hmask, __bf16 *Dout,
+                           __bf16 *Tout, int lo, int hi)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int MT = CO / 16;
+    constexpr int NT = kCnnWin / 16;
+    const int kq = 8 * (lane >> 4);
+    for (int tile = wv; tile < MT * NT; tile += 4) {
+        const int mt = tile % MT;
+        const int nt = tile / MT;
+        const int m = mt * 16 + (lane & 15);
+        const int n = nt * 16 + (lane & 15);
+        const f32x4 acc = mfma_tile<KP / 32>(Wf + m * KP + kq, D + (n + kCnnGuard - 2) * CI + kq);
+        const int mo = mt * 16 + 4 * (lane >> 4);
+        const bool inside = n >= lo && n < hi;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool open = inside && (float)Hmask[(n + kCnnGuard) * CO + mo + j] > 0.0f;
+            const __bf16 o = to_bf16(open ? acc[j] : 0.0f);
+            if (Dout)
+                Dout[(n + kCnnGuard) * CO + mo + j] = o;
+            Tout[(mo + j) * kCnnWin + n] = o;
+        }
+    }
+}
+
+// Weight-gradient tiles of one layer, accumulated in registers: tile i of
+// wave wv is tile wv + 4 i of the layer's (COUT / 16) x (KP / 16) tiles.
+template <int CIN, int COUT, int KP, int NPW>
+__device__ __forceinline__ void weight_grad(f32x4 (&acc)[NPW], const __bf16 *T, const __bf16 *X)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int MT = COUT / 16;
+    constexpr int TILES = MT * (KP / 16);
+    const int kq = 8 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+        const int tile = wv + 4 * i;
+        if (tile < TILES) {
+            const int mt = tile % MT;
+            const int nt = tile / MT;
+            const __bf16 *a_row = T + (mt * 16 + (lane & 15)) * kCnnWin + kq;
+            const __bf16 *b_col = X + (kq + kCnnGuard - 2) * CIN + nt * 16 + (lane & 15);
+            f32x4 c = acc[i];
+#pragma unroll
+            for (int ks = 0; ks < kCnnWin / 32; ++ks) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(a_row + 32 * ks);
+                bf16x8 bv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    bv[e] = b_col[(32 * ks + e) * CIN];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+            }
+            acc[i] = c;
+        }
+    }
+}
+
+template <int COUT, int KP, int NPW>
+__device__ __forceinline__ void store_weight_grad(const f32x4 (&acc)[NPW], float *out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int MT = COUT / 16;
+    constexpr int TILES = MT * (KP / 16);
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+        const int tile = wv + 4 * i;
+        if (tile < TILES) {
+            const int o = (tile % MT) * 16 + 4 * (lane >> 4);
+            const int k = (tile / MT) * 16 + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                out[(o + j) * KP + k] = acc[i][j];
+        }
+    }
+}
+
+// Sum of a channel-major dP over this thread's share of positions: 16
+// channels -> 16 threads x 8 positions per channel, 32 -> 8 x 16.
+template <int C>
+__device__ __forceinline__ float bias_share(const __bf16 *T)
+{
+    constexpr int per = kCnnWin * C / kBlock;
+    const int c = threadIdx.x / (kBlock / C);
+    const int n0 = (threadIdx.x % (kBlock / C)) * per;
+    float v = 0.0f;
+#pragma unroll
+    for (int i = 0; i < per; ++i)
+        v += (float)T[c * kCnnWin + n0 + i];
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cnn_grad(CnnTrainArgs a)
+{
+    __shared__ CnnGradLds s;
+    const int tid = threadIdx.x;
+    const __bf16 *W = reinterpret_cast<const __bf16 *>(a.model);
+    const __bf16 *Wf = reinterpret_cast<const __bf16 *>(a.model + kCnnFlipOff);
+    const float *mf = reinterpret_cast<const float *>(a.model + kCnnFloatsOff);
+    for (int i = tid; i < 128; i += kBlock)
+        s.fb[i] = i < kCnnFloats ? mf[i] : 0.0f;
+    zero_guards(s.x0, 24);
+    zero_guards(s.h1, 16);
+    zero_guards(s.h2, 32);
+    zero_guards(s.h3, 32);
+    zero_guards(s.h4, 16);
+    zero_guards(s.d32, 32);
+
+    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 g1[2], g2[3], g3[5], g4[3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        g1[i] = zero4;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        g2[i] = g4[i] = zero4;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        g3[i] = zero4;
+    float pb1 = 0.0f, pb2 = 0.0f, pb3 = 0.0f, pb4 = 0.0f, pw5 = 0.0f, pb5 = 0.0f, ploss = 0.0f;
+
+    for (int wi = blockIdx.x; wi < a.n; wi += gridDim.x) {
+        const int lo = uniform_int(a.range[2 * wi]);
+        const int hi = uniform_int(a.range[2 * wi + 1]);
+        load_window(s.x0, a.win + (int64_t)wi * (kCnnLines * kCnnWin * 3), lo, hi);
+        __syncthreads();
+        window_forward(W, s.fb, s.x0, s.h1, s.h2, s.h3, s.h4, s.z, lo, hi);
+
+        // loss and dL/dz at the central positions inside the strip
+        if (tid < kCnnWin) {
+            const int n = tid;
+            float dz = 0.0f;
+            if (n >= kCnnHalo && n < kCnnWin - kCnnHalo && n >= lo && n < hi) {
+                const int64_t j = (int64_t)wi * kCnnOut + (n - kCnnHalo);
+                const float wt = a.weight[j] * a.scale;
+                const float t = a.target[j];
+                const float z = s.z[n];
+                dz = wt * (sigmoid(z) - t);
+                // soft binary cross entropy in its logit form
+                ploss += wt * (fmaxf(z, 0.0f) - z * t + log1pf(expf(-fabsf(z))));
+            }
+            pb5 += dz;
+            s.z[n] = dz;
+        }
+        __syncthreads();
+        // layer 5 (1x1): dW5, and dP4 = [h4 > 0] w5 dz, in place of h4
+        {
+            const int c = tid & 15;
+            const float w5 = s.fb[kCnnW5Off + c];
+#pragma unroll
+            for (int i = 0; i < kCnnWin * 16 / kBlock; ++i) {
+                const int n = (tid >> 4) + 16 * i;
+                const float h = (float)s.h4[(n + kCnnGuard) * 16 + c];
+                const float dz = s.z[n];
+                pw5 = fmaf(dz, h, pw5);
+                const __bf16 v = to_bf16(h > 0.0f ? w5 * dz : 0.0f);
+                s.h4[(n + kCnnGuard) * 16 + c] = v;
+                s.t[0][c * kCnnWin + n] = v;
+            }
+        }
+        __syncthreads();
+        // layer 4: 32 -> 16
+        weight_grad<32, 16, 160, 3>(g4, s.t[0], s.h3);
+        input_grad<16, 32, 96>(Wf + kCnnFOff[2], s.h4, s.h3, s.d32, s.t[1], lo, hi);
+        pb4 += bias_share<16>(s.t[0]);
+        __syncthreads();
+        // layer 3: 32 -> 32
+        weight_grad<32, 32, 160, 5>(g3, s.t[1], s.h2);
+        input_grad<32, 32, 160>(Wf + kCnnFOff[1], s.d32, s.h2, s.h3, s.t[0], lo, hi);
+        pb3 += bias_share<32>(s.t[1]);
+        __syncthreads();
+        // layer 2: 16 -> 32
+        weight_grad<16, 32, 96, 3>(g2, s.t[0], s.h1);
+        input_grad<32, 16, 160>(Wf + kCnnFOff[0], s.h3, s.h1, nullptr, s.t[1], lo, hi);
+        pb2 += bias_share<32>(s.t[0]);
+        __syncthreads();
+        // layer 1: 24 -> 16
+        weight_grad<24, 16, 128, 2>(g1, s.t[1], s.x0);
+        pb1 += bias_share<16>(s.t[1]);
+        __syncthreads();
+    }
+
+    float *out = a.partial + (int64_t)blockIdx.x * kCnnGradStride;
+    store_weight_grad<16, 128, 2>(g1, out + kCnnWOff[0]);
+    store_weight_grad<32, 96, 3>(g2, out + kCnnWOff[1]);
+    store_weight_grad<32, 160, 5>(g3, out + kCnnWOff[2]);
+    store_weight_grad<16, 160, 3>(g4, out + kCnnWOff[3]);
+
+    float *red = reinterpret_cast<float *>(&s.t[0][0]);   // 7 x 256 floats
+    red[0 * kBlock + tid] = pb1;
+    red[1 * kBlock + tid] = pb2;
+    red[2 * kBlock + tid] = pb3;
+    red[3 * kBlock + tid] = pb4;
+    red[4 * kBlock + tid] = pw5;
+    red[5 * kBlock + tid] = pb5;
+    red[6 * kBlock + tid] = ploss;
+    __syncthreads();
+    if (tid < 128) {
+        const int r = tid;
+        float v = 0.0f;
+        if (r < 16) {                       // b1: threads 16 r .. 16 r + 15
+            for (int i = 0; i < 16; ++i)
+                v += red[0 * kBlock + 16 * r + i];
+        } else if (r < 48) {                // b2: threads 8 o .. 8 o + 7
+            for (int i = 0; i < 8; ++i)
+                v += red[1 * kBlock + 8 * (r - 16) + i];
+        } else if (r < 80) {                // b3
+            for (int i = 0; i < 8; ++i)
+                v += red[2 * kBlock + 8 * (r - 48) + i];
+        } else if (r < 96) {                // b4
+            for (int i = 0; i < 16; ++i)
+                v += red[3 * kBlock + 16 * (r - 80) + i];
+        } else if (r < 112) {               // w5[c]: threads c + 16 i
+            for (int i = 0; i < 16; ++i)
+                v += red[4 * kBlock + (r - 96) + 16 * i];
+        } else if (r == 112 || r == 113) {  // b5, loss
+            for (int i = 0; i < kBlock; ++i)
+                v += red[(r == 112 ? 5 : 6) * kBlock + i];
+        }
+        out[kCnnWElems + r] = v;
+    }
+}
+
+// Parameter layout of the model file (float32): per layer W[o][c][t], b[o].
+struct FileLayer {
+    int cin, cout, kp, woff, fw, fb;
+};
+__device__ __forceinline__ FileLayer file_layer(int l)
+{
+    switch (l) {
+    case 0: return {24, 16, 128, kCnnWOff[0], 0, 1920};
+    case 1: return {16, 32, 96, kCnnWOff[1], 1936, 4496};
+    case 2: return {32, 32, 160, kCnnWOff[2], 4528, 9648};
+    default: return {32, 16, 160, kCnnWOff[3], 9680, 12240};
+    }
+}
+constexpr int kFileW5 = 12256;
+constexpr int kFileB5 = 12272;
+
+// Sum the workgroup partials; scatter to the model-file order.
+__global__ __launch_bounds__(kBlock) void k_cnn_reduce(const float *partial, int grid,
+                                                       float *grad, float *loss)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kCnnGradStride)
+        return;
+    float v = 0.0f;
+    for (int g = 0; g < grid; ++g)
+        v += partial[(int64_t)g * kCnnGradStride + i];
+    if (i < kCnnWElems) {
+        const int l = i < kCnnWOff[1] ? 0 : i < kCnnWOff[2] ? 1 : i < kCnnWOff[3] ? 2 : 3;
+        const FileLayer L = file_layer(l);
+        const int o = (i - L.woff) / L.kp;
+        const int k = (i - L.woff) - o * L.kp;
+        if (k >= 5 * L.cin)
+            return;
+        const int t = k / L.cin, c = k - t * L.cin;
+        grad[L.fw + (o * L.cin + c) * 5 + t] = v;
+        return;
+    }
+    const int r = i - kCnnWElems;
+    if (r < 96) {
+        const int l = r < kCnnBOff[1] ? 0 : r < kCnnBOff[2] ? 1 : r < kCnnBOff[3] ? 2 : 3;
+        grad[file_layer(l).fb + r - kCnnBOff[l]] = v;
+    } else if (r < 112) {
+        grad[kFileW5 + r - 96] = v;
+    } else if (r == 112) {
+        grad[kFileB5] = v;
+    } else if (r == 113) {
+        loss[0] = v;
+    }
+}
+
+// SGD with momentum: m = mu m + g, p -= lr m.
+__global__ __launch_bounds__(kBlock) void k_cnn_sgd(float *master, float *mom, const float *grad,
+                                                    float lr, float mu)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kCnnParams)
+        return;
+    const float m = mu * mom[i] + grad[i];
+    mom[i] = m;
+    master[i] -= lr * m;
+}
+
+// Device model block from float32 master weights: every slot (padding
+// included) is written.
+__global__ __launch_bounds__(kBlock) void k_cnn_pack(const float *master, uint8_t *model)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    __bf16 *w = reinterpret_cast<__bf16 *>(model);
+    float *fb = reinterpret_cast<float *>(model + kCnnFloatsOff);
+    __bf16 *wf = reinterpret_cast<__bf16 *>(model + kCnnFlipOff);
+    if (i < kCnnWElems) {
+        const int l = i < kCnnWOff[1] ? 0 : i < kCnnWOff[2] ? 1 : i < kCnnWOff[3] ? 2 : 3;
+        const FileLayer L = file_layer(l);
+        const int o = (i - L.woff) / L.kp;
+        const int k = (i - L.woff) - o * L.kp;
+        float v = 0.0f;
+        if (k < 5 * L.cin) {
+            const int t = k / L.cin, c = k - t * L.cin;
+            v = master[L.fw + (o * L.cin + c) * 5 + t];
+        }
+        w[i] = to_bf16(v);
+        return;
+    }
+    int r = i - kCnnWElems;
+    if (r < 128) {
+        float v = 0.0f;
+        if (r < 96) {
+            const int l = r < kCnnBOff[1] ? 0 : r < kCnnBOff[2] ? 1 : r < kCnnBOff[3] ? 2 : 3;
+            v = master[file_layer(l).fb + r - kCnnBOff[l]];
+        } else if (r < 112) {
+            v = (float)to_bf16(master[kFileW5 + r - 96]);
+        } else if (r == 112) {
+            v = master[kFileB5];
+        }
+        fb[r] = v;
+        return;
+    }
+    r -= 128;
+    if (r < kCnnFElems) {
+        // Wf_l[c][t' C_out + o] = W_l[o][c][4 - t'] for layers 2, 3, 4
+        const int q = r < kCnnFOff[1] ? 0 : r < kCnnFOff[2] ? 1 : 2;
+        const FileLayer L = file_layer(q + 1);
+        const int kpf = q == 2 ? 96 : 160;
+        const int c = (r - kCnnFOff[q]) / kpf;
+        const int k = (r - kCnnFOff[q]) - c * kpf;
+        float v = 0.0f;
+        if (k < 5 * L.cout) {
+            const int tp = k / L.cout, o = k - tp * L.cout;
+            v = master[L.fw + (o * L.cin + c) * 5 + (4 - tp)];
+        }
+        wf[r] = to_bf16(v);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_mfma_probe(float *out, hipStream_t s)
@@ -290,6 +684,45 @@ hipError_t launch_cnn_strips(const CnnStripArgs &a, hipStream_t s)
     if (a.n_items <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_cnn_strips, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ca
+
+namespace ca {
+
+hipError_t launch_cnn_grad(const CnnTrainArgs &a, int grid, hipStream_t s)
+{
+    if (grid <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cnn_grad, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_reduce(const float *partial, int grid, float *grad_out, float *loss_out,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnn_reduce, dim3((kCnnGradStride + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, partial, grid, grad_out, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_update(float *master, float *momentum, const float *grad, float lr,
+                             float mom, uint8_t *model, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnn_sgd, dim3((kCnnParams + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       master, momentum, grad, lr, mom);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_cnn_pack(master, model, s);
+}
+
+hipError_t launch_cnn_pack(const float *master, uint8_t *model, hipStream_t s)
+{
+    constexpr int slots = kCnnWElems + 128 + kCnnFElems;
+    hipLaunchKernelGGL(k_cnn_pack, dim3((slots + kBlock - 1) / kBlock), dim3(kBlock), 0, s, master,
+                       model);
     return hipGetLastError();
 }
 

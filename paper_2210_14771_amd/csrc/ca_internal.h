@@ -102,6 +102,10 @@ size_t fused_lds_bytes(int sg_len, int line_pitch);
 hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s);
 hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s);
+// out[f] = fallback[f] (reason + CA_REASON_FALLBACK) where out[f] has fewer
+// than 3 points or inliers < frac * n_points.
+hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, float frac,
+                           hipStream_t s);
 hipError_t fused_occupancy(size_t lds_bytes, int *blocks_per_cu);
 
 }  // namespace ca

@@ -883,6 +883,22 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
     }
 }
 
+// Learned-scorer fallback: a frame whose best circle explains less than
+// `frac` of its kept points takes the handcrafted pipeline's result.
+__global__ __launch_bounds__(kBlock) void k_fallback(ca_result *out, const ca_result *fb, int n,
+                                                     float frac)
+{
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= n)
+        return;
+    const ca_result a = out[f];
+    if (a.n_points < 3 || (float)a.inliers < frac * (float)a.n_points) {
+        ca_result b = fb[f];
+        b.reason += CA_REASON_FALLBACK;
+        out[f] = b;
+    }
+}
+
 }  // namespace
 
 size_t strip_lds_bytes(int sg_len, int line_pitch)
@@ -919,6 +935,16 @@ hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStrea
     if (a.se.n_frames <= 0)
         return hipSuccess;
     hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, float frac,
+                           hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_fallback, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, out,
+                       fallback, n, frac);
     return hipGetLastError();
 }
 

@@ -86,3 +86,21 @@ def frame_errors(specs, cx, cy, r, valid) -> np.ndarray:
         est = (float(cx[i]), float(cy[i]), float(r[i])) if bool(valid[i]) else None
         out.append(normalised_hausdorff(s.width, s.height, gt, est))
     return np.asarray(out)
+
+
+def accuracy(est, frames_dev, specs, params, uids=None) -> dict:
+    """Run the estimator once on device frames and summarise its error
+    against the ground truth (plus the valid and fallback shares)."""
+    import torch
+    B = len(specs)
+    res = est.estimate_area(frames_dev, params, list(range(B)) if uids is None else uids)
+    torch.cuda.synchronize()
+    raw = res.raw.cpu().numpy()
+    cx, cy, r = (raw[:, k].view(np.float32) for k in range(3))
+    valid = raw[:, 6] != 0
+    errs = frame_errors(specs, cx, cy, r, valid)
+    out = summarise(errs)
+    out["valid_frac"] = float(valid.mean())
+    out["fallback_frac"] = float((raw[:, 7] >= 256).mean())
+    return out
+

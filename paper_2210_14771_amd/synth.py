@@ -72,18 +72,17 @@ def _smooth_field(rng: np.random.Generator, h: int, w: int, cell: float) -> np.n
     return _interp_matrix(h, gh) @ g @ _interp_matrix(w, gw).T
 
 
-def _content(rng: np.random.Generator, spec: FrameSpec, rho: np.ndarray | None) -> np.ndarray:
-    """Tissue-like smooth colour field, float32 (H, W, 3), mean luma near spec.mean_luma."""
+def _content_from_grids(spec: FrameSpec, grids, rho: np.ndarray | None) -> np.ndarray:
+    """Noise-free tissue-like colour field, float32 (H, W, 3), mean luma near
+    spec.mean_luma, from the control grids of ``smooth_grids``."""
     h, w = spec.height, spec.width
-    cell = max(h, w) / 10.0
-    base = _smooth_field(rng, h, w, cell)
-    fine = _smooth_field(rng, h, w, cell / 4.0)
-    lum = spec.mean_luma * (1.0 + 0.18 * base + 0.06 * fine)
-    # per-frame reddish tint; channel gains chosen so BT.601 luma of the gains is 1
-    tint = np.array([1.30, 0.88, 0.72], dtype=np.float32)
-    tint = tint * (1.0 + 0.05 * rng.standard_normal(3).astype(np.float32))
-    tint /= float(0.299 * tint[0] + 0.587 * tint[1] + 0.114 * tint[2])
-    chroma = [_smooth_field(rng, h, w, cell) for _ in range(3)]
+    base_g, fine_g, chroma_g, tint = grids
+
+    def field(g):
+        return _interp_matrix(h, g.shape[0]) @ g @ _interp_matrix(w, g.shape[1]).T
+
+    lum = spec.mean_luma * (1.0 + 0.18 * field(base_g) + 0.06 * field(fine_g))
+    chroma = [field(g) for g in chroma_g]
     img = np.empty((h, w, 3), dtype=np.float32)
     for c in range(3):
         img[..., c] = lum * np.float32(tint[c]) * (1.0 + np.float32(0.08) * chroma[c])
@@ -96,8 +95,28 @@ def _content(rng: np.random.Generator, spec: FrameSpec, rho: np.ndarray | None) 
             scale = spec.r
         fall = 1.0 - spec.vignette * np.minimum(rho / scale, 1.0) ** 2
         img *= fall[..., None]
+    return img
+
+
+def _content(rng: np.random.Generator, spec: FrameSpec, rho: np.ndarray | None) -> np.ndarray:
+    """Tissue-like smooth colour field with pixel noise (sigma 2), float32 (H, W, 3)."""
+    img = _content_from_grids(spec, smooth_grids(rng, spec), rho)
     img += 2.0 * rng.standard_normal(img.shape, dtype=np.float32)
     return img
+
+
+def render_noise_free(spec: FrameSpec, grids) -> np.ndarray:
+    """The frame of ``render`` without its pixel and border noise (float32,
+    before rounding), from given control grids: the image model's
+    deterministic part, against which a device renderer can be checked."""
+    h, w = spec.height, spec.width
+    if spec.kind == KIND_NOBORDER:
+        return _content_from_grids(spec, grids, None)
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float32)
+    rho = np.hypot(xx - np.float32(spec.cx), yy - np.float32(spec.cy))
+    img = _content_from_grids(spec, grids, rho)
+    alpha = ndtr((np.float32(spec.r) - rho) / np.float32(spec.blur_sigma)).astype(np.float32)
+    return alpha[..., None] * img + (1.0 - alpha)[..., None] * np.float32(6.0)
 
 
 def render(spec: FrameSpec, rng: np.random.Generator) -> np.ndarray:
@@ -215,3 +234,105 @@ def make_batch(wl: Workload, n_frames: int | None = None, start: int = 0,
         frames.append(f)
         specs.append(s)
     return np.stack(frames), specs
+
+
+# ------------------------------------------------------------ hard frames --
+#
+# Failure cases of the handcrafted score (Section 1.1, Figure 3): a dark rim
+# that leaves only a small luma step at the edge, strong border noise,
+# specular blobs and white text overlays in the border.  Hard frames are
+# rendered on the device (the training set is far too large for a CPU
+# renderer); this module draws their parameters.
+
+GLYPH_W, GLYPH_H = 5, 7        # dot-matrix glyph cells
+
+
+@dataclasses.dataclass
+class HardExtras:
+    """Extra ground-truth-free distractors of a hard frame."""
+    edge_step: float                      # content luma at the rim = 6 + edge_step (0: off)
+    blobs: list                           # (x, y, radius, amplitude) in the border
+    text_x: float = 0.0                   # top-left corner of the text block
+    text_y: float = 0.0
+    text_scale: int = 0                   # pixels per glyph cell (0: no text)
+    text_lines: int = 0
+    text_chars: int = 0
+    glyphs: np.ndarray | None = None      # uint64 [lines * chars], 35 bits each
+
+
+def _in_border(spec: FrameSpec, x: float, y: float, margin: float) -> bool:
+    return bool(np.hypot(x - spec.cx, y - spec.cy) > spec.r + margin)
+
+
+def draw_hard(rng: np.random.Generator, spec: FrameSpec,
+              edge_step: tuple[float, float] = (10.0, 25.0)) -> HardExtras:
+    """Draw the distractors of a hard frame (none in a frame without border)."""
+    ex = HardExtras(edge_step=float(rng.uniform(*edge_step)), blobs=[])
+    if not spec.has_border:
+        ex.edge_step = 0.0
+        return ex
+    w, h = spec.width, spec.height
+    margin = 3.0 * spec.blur_sigma + 2.0
+    for _ in range(int(rng.integers(0, 4))):
+        for _ in range(50):
+            x, y = float(rng.uniform(0, w - 1)), float(rng.uniform(0, h - 1))
+            rad = float(rng.uniform(3.0, 15.0))
+            if _in_border(spec, x, y, margin + 2.0 * rad):
+                ex.blobs.append((x, y, rad, float(rng.uniform(120.0, 250.0))))
+                break
+    if rng.uniform() < 0.8:
+        scale = int(rng.integers(2, 4))
+        lines = int(rng.integers(1, 5))
+        chars = int(rng.integers(4, 15))
+        bw = chars * (GLYPH_W + 1) * scale
+        bh = lines * (GLYPH_H + 2) * scale
+        corners = [(4.0, 4.0), (w - 5.0 - bw, 4.0), (4.0, h - 5.0 - bh), (w - 5.0 - bw, h - 5.0 - bh)]
+        order = rng.permutation(4)
+        for ci in order:
+            x0, y0 = corners[ci]
+            if x0 < 0 or y0 < 0:
+                continue
+            box = [(x0, y0), (x0 + bw, y0), (x0, y0 + bh), (x0 + bw, y0 + bh)]
+            if all(_in_border(spec, x, y, margin) for x, y in box) and \
+                    _in_border(spec, x0 + bw / 2, y0 + bh / 2, margin):
+                ex.text_x, ex.text_y = x0, y0
+                ex.text_scale, ex.text_lines, ex.text_chars = scale, lines, chars
+                bits = rng.integers(0, 2, (lines * chars, GLYPH_W * GLYPH_H), dtype=np.uint64)
+                bits[rng.uniform(size=lines * chars) < 0.15] = 0     # spaces
+                ex.glyphs = (bits << np.arange(GLYPH_W * GLYPH_H, dtype=np.uint64)).sum(
+                    axis=1).astype(np.uint64)
+                break
+    return ex
+
+
+def smooth_grids(rng: np.random.Generator, spec: FrameSpec):
+    """Control grids of the content's smooth fields (base, fine, 3 chroma),
+    blurred and normalised exactly as the CPU renderer does before its
+    bilinear interpolation, and the per-frame channel tint."""
+    h, w = spec.height, spec.width
+    cell = max(h, w) / 10.0
+
+    def grid(c):
+        gh = max(3, int(round(h / c)) + 2)
+        gw = max(3, int(round(w / c)) + 2)
+        g = rng.standard_normal((gh, gw), dtype=np.float32)
+        g = (g + np.roll(g, 1, 0) + np.roll(g, -1, 0)) / 3.0
+        g = (g + np.roll(g, 1, 1) + np.roll(g, -1, 1)) / 3.0
+        g /= max(float(g.std()), 1e-6)
+        return g.astype(np.float32)
+
+    base = grid(cell)
+    fine = grid(cell / 4.0)
+    tint = np.array([1.30, 0.88, 0.72], dtype=np.float32)
+    tint = tint * (1.0 + 0.05 * rng.standard_normal(3).astype(np.float32))
+    tint /= float(0.299 * tint[0] + 0.587 * tint[1] + 0.114 * tint[2])
+    chroma = [grid(cell) for _ in range(3)]
+    return base, fine, chroma, tint
+
+
+# Hard 1080p frames: the headline mix with border noise sigma up to 12 and the
+# distractors above.
+HARD_1080p = Workload(4, 1920, 1080, 64, (60.0, 25.0, 10.0), (2.0, 12.0), (1.0, 3.0), (0.0, 0.4),
+                      None, 32, 32, 1024)
+WORKLOADS[4] = HARD_1080p
+

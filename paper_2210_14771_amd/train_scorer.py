@@ -1,0 +1,170 @@
+"""Train the learned strip scorer on the GPU (Section 2.2.4, training).
+
+The paper trains its CNN with a soft binary cross entropy against edge maps
+blurred with a Gaussian of sigma 3, by SGD, and keeps the model with the
+best validation loss.  Here every step draws a fresh batch of synthetic
+1080p frames (plain and hard, device-rendered), cuts the 8-line strips of
+random rows and columns into windows, labels each strip pixel with the soft
+edge label of the ground-truth circle, and runs the library's own forward,
+backward and SGD kernels (ca_cnn_gradients, ca_cnn_sgd_step).  Nothing of
+the step runs on the host except drawing the frames' parameters.
+
+    python -m paper_2210_14771_amd.train_scorer --steps 3125 --out paper_2210_14771_amd/models
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import api, synth, synth_gpu
+
+LAYERS = [(24, 16, 5), (16, 32, 5), (32, 32, 5), (32, 16, 5), (16, 1, 1)]
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+MODEL_FILE = "scorer_1d.npy"
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, in model-file order (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co, k in LAYERS:
+        parts.append((rng.standard_normal(co * ci * k) * math.sqrt(2.0 / (ci * k))).astype(np.float32))
+        parts.append(np.zeros(co, dtype=np.float32))
+    return np.concatenate(parts)
+
+
+def load_model(path: str | None = None) -> np.ndarray:
+    """The committed trained scorer (float32, model-file order)."""
+    path = path or os.path.join(MODEL_DIR, MODEL_FILE)
+    p = np.load(path, allow_pickle=False)
+    if p.dtype != np.float32 or p.shape != (12273,):
+        raise ValueError(f"{path}: not a scorer model")
+    return p
+
+
+def draw_frames(stream_plain: int, stream_hard: int, first: int, n: int, hard_frac: float,
+                rng: np.random.Generator):
+    """n frame recipes: a hard_frac share from the hard stream, the rest plain."""
+    recs = []
+    for i in range(first, first + n):
+        if rng.uniform() < hard_frac:
+            recs.append(synth_gpu.draw_recipe(synth.HARD_1080p, stream_hard, i, True))
+        else:
+            recs.append(synth_gpu.draw_recipe(synth.HD_1080p, stream_plain, i, False))
+    return recs
+
+
+def draw_windows(recs, strips_per_frame: int, rng: np.random.Generator) -> np.ndarray:
+    """Windows tiling strips through random rows and columns of every frame."""
+    out = []
+    for f, rc in enumerate(recs):
+        w, h = rc.spec.width, rc.spec.height
+        for _ in range(strips_per_frame):
+            hz = bool(rng.uniform() < 0.5)
+            line = int(rng.integers(0, h if hz else w))
+            out.append(synth_gpu.strip_windows(f, hz, line, w if hz else h))
+    return np.concatenate(out)
+
+
+def positions_inside(desc: np.ndarray, recs) -> int:
+    """Central window positions that lie inside their strips."""
+    L = np.array([recs[f].spec.width if hz else recs[f].spec.height for f, hz, _, _ in desc])
+    lo = np.maximum(desc[:, 3] + 8, 0)
+    hi = np.minimum(desc[:, 3] + 120, L)
+    return int(np.maximum(hi - lo, 0).sum())
+
+
+class Batch:
+    def __init__(self, recs, desc, edge_boost):
+        self.dev = synth_gpu.DeviceRecipes(recs)
+        self.win, self.rng, self.tgt, self.wt = self.dev.render_windows(desc, edge_boost)
+        self.scale = 1.0 / max(positions_inside(desc, recs), 1)
+
+    def tensors(self):
+        return self.win, self.rng, self.tgt, self.wt
+
+
+def train(steps: int = 3125, frames_per_step: int = 64, strips_per_frame: int = 16,
+          lr: float = 0.5, momentum: float = 0.9, warmup: int = 100, hard_frac: float = 0.5,
+          edge_boost: float = 0.0, seed: int = 0, valid_every: int = 100, valid_frames: int = 128,
+          log=print, est: api.Estimator | None = None):
+    """Returns (best master weights, log dict)."""
+    import torch
+    own = est is None
+    est = est or api.Estimator(0)
+    rng = np.random.default_rng(seed)
+    est.set_model(init_params(seed))
+    vrng = np.random.default_rng(seed + 1)
+    vrecs = draw_frames(synth_gpu.VALID_PLAIN, synth_gpu.VALID_HARD, 0, valid_frames, hard_frac,
+                        vrng)
+    valid = Batch(vrecs, draw_windows(vrecs, strips_per_frame, vrng), edge_boost)
+    history = []
+    best = (math.inf, None, -1)
+    t0 = time.time()
+    frames_seen = 0
+    for step in range(steps + 1):
+        if step % valid_every == 0 or step == steps:
+            _, vloss = est.cnn_gradients(*valid.tensors(), valid.scale)
+            v = float(vloss.item())
+            history.append({"step": step, "valid_loss": v, "frames": frames_seen,
+                            "seconds": round(time.time() - t0, 1)})
+            log(f"step {step} valid loss {v:.5f} frames {frames_seen} "
+                f"({time.time() - t0:.0f} s)")
+            if v < best[0]:
+                best = (v, est.get_model(), step)
+        if step == steps:
+            break
+        recs = draw_frames(synth_gpu.TRAIN_PLAIN, synth_gpu.TRAIN_HARD, step * frames_per_step,
+                           frames_per_step, hard_frac, rng)
+        b = Batch(recs, draw_windows(recs, strips_per_frame, rng), edge_boost)
+        grad, loss = est.cnn_gradients(*b.tensors(), b.scale)
+        if step < warmup:
+            lr_t = lr * (step + 1) / warmup
+        else:
+            lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * (step - warmup) / max(steps - warmup, 1)))
+        est.cnn_sgd_step(grad, lr_t, momentum)
+        frames_seen += frames_per_step
+        if step % 25 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    info = {"steps": steps, "frames": frames_seen, "frames_per_step": frames_per_step,
+            "strips_per_frame": strips_per_frame, "lr": lr, "momentum": momentum,
+            "warmup": warmup, "hard_frac": hard_frac, "edge_boost": edge_boost, "seed": seed,
+            "best_step": best[2], "best_valid_loss": best[0], "history": history,
+            "seconds": round(time.time() - t0, 1)}
+    if own:
+        est.close()
+    return best[1], info
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--steps", type=int, default=3125)
+    ap.add_argument("--frames-per-step", type=int, default=64)
+    ap.add_argument("--strips-per-frame", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=0.5)
+    ap.add_argument("--momentum", type=float, default=0.9)
+    ap.add_argument("--hard-frac", type=float, default=0.5)
+    ap.add_argument("--edge-boost", type=float, default=0.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--valid-every", type=int, default=100)
+    ap.add_argument("--out", default=MODEL_DIR)
+    a = ap.parse_args()
+    params, info = train(a.steps, a.frames_per_step, a.strips_per_frame, a.lr, a.momentum,
+                         hard_frac=a.hard_frac, edge_boost=a.edge_boost, seed=a.seed,
+                         valid_every=a.valid_every,
+                         log=lambda s: print(s, flush=True))
+    os.makedirs(a.out, exist_ok=True)
+    np.save(os.path.join(a.out, MODEL_FILE), params.astype(np.float32), allow_pickle=False)
+    with open(os.path.join(a.out, "scorer_1d_training.json"), "w") as f:
+        json.dump(info, f, indent=1)
+    print(json.dumps({k: v for k, v in info.items() if k != "history"}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,3 +104,63 @@ def test_edge_target_closed_form():
     assert t[70] == 1.0 and t[130] == 1.0
     assert abs(t[73] - math.exp(-9 / 18)) < 1e-12
     assert np.all(cnn.edge_target(50, 5, False, None) == 0)
+
+
+class _RoundForward(torch.autograd.Function):
+    """bfloat16 storage of an activation; the gradient passes unchanged."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundBackward(torch.autograd.Function):
+    """Identity forward; the gradient is stored in bfloat16."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_backward_signals_match_autograd():
+    """The grad_bf16 mode: autograd with explicit bfloat16 roundings of the
+    stored activations and of the gradients at the hidden pre-activations,
+    masked windows and per-position loss weights, a given scale."""
+    rng = np.random.default_rng(8)
+    params = [(w, b + rng.normal(0, 0.1, b.shape)) for w, b in cnn.init_params(9)]
+    L = 64
+    xs = [cnn.bf16(rng.standard_normal((24, L))) for _ in range(3)]
+    ts = [rng.uniform(0, 1, L) for _ in range(3)]
+    masks = [np.ones(L, bool), np.arange(L) < 40, np.arange(L) >= 11]
+    weights = [rng.uniform(0, 2, L) * (rng.uniform(size=L) > 0.2) for _ in range(3)]
+    scale = 1.0 / 77.0
+    loss, grads = cnn.loss_and_grads(xs, ts, params, True, masks, weights, scale, grad_bf16=True)
+    tp = [(torch.tensor(w, requires_grad=True), torch.tensor(b, requires_grad=True))
+          for w, b in params]
+    tl = 0
+    for x, t, m, wt in zip(xs, ts, masks, weights):
+        mt = torch.tensor(m)
+        h = torch.where(mt, torch.tensor(x), torch.zeros(()))[None]
+        for w, b in tp[:-1]:
+            a = torch.nn.functional.conv1d(h, w, b, padding=2)
+            a = torch.where(mt, a, torch.zeros(()))
+            h = _RoundForward.apply(torch.relu(_RoundBackward.apply(a)))
+        z = torch.nn.functional.conv1d(h, tp[-1][0], tp[-1][1])[0, 0]
+        tl = tl + scale * (torch.tensor(wt) * torch.nn.functional.binary_cross_entropy_with_logits(
+            z, torch.tensor(t), reduction="none")).sum()
+    tl.backward()
+    assert abs(tl.item() - loss) < 1e-9
+    for (gw, gb), (w, b) in zip(grads, tp):
+        np.testing.assert_allclose(gw, w.grad.numpy(), rtol=1e-9, atol=1e-15)
+        np.testing.assert_allclose(gb, b.grad.numpy(), rtol=1e-9, atol=1e-15)
+    # and the rounding matters: the exact chain rule differs
+    _, exact = cnn.loss_and_grads(xs, ts, params, True, masks, weights, scale)
+    assert any(not np.array_equal(a[0], b[0]) for a, b in zip(grads, exact))
