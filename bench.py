@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
     ap.add_argument("--lag", type=int, default=None)
     ap.add_argument("--queues", type=int, default=None)
+    ap.add_argument("--learned-steps", type=int, default=100,
+                    help="timed calls of the learned scorer (0: skip the learned section)")
+    ap.add_argument("--hard-frames", type=int, default=64,
+                    help="device-rendered hard 1080p frames for the accuracy comparison")
+    ap.add_argument("--mixed-steps", type=int, default=20,
+                    help="timed graph replays of the 512-frame uneven batch (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -78,6 +84,146 @@ def measured_traffic(kernel: str):
     if not m or not h or not sha.startswith(h.group(1)):
         return None
     return int(m.group(1))
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix
+
+
+def cnn_flops_per_frame(w: int, h: int, n_h: int, n_v: int) -> float:
+    """Multiply-adds x 2 of the learned scorer at every strip position once:
+    four width-5 convolutions 24-16-32-32-16 and the 1x1 layer."""
+    macs = 5 * (24 * 16 + 16 * 32 + 32 * 32 + 32 * 16) + 16
+    return 2.0 * macs * (n_h * w + n_v * h)
+
+
+def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
+    """The learned scorer (with the handcrafted fallback) on the same frames:
+    throughput, kernel roofline, accuracy next to the plain scorer on the
+    headline batch and on device-rendered hard frames."""
+    import numpy as np
+    import torch
+    from paper_2210_14771_amd import api, evaluate, synth, synth_gpu, train_scorer
+    path = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE)
+    if args.learned_steps <= 0 or not os.path.exists(path):
+        return None
+    B, W, H = len(specs), specs[0].width, specs[0].height
+    est.set_model(train_scorer.load_model(path))
+    lp = api.default_params(**kw, scorer=1, fallback_inlier_frac=0.5)
+    lp_nofb = api.default_params(**kw, scorer=1)
+    K = args.learned_steps
+    for i in range(5):
+        est.estimate_area(resident[i % len(resident)], lp, uids, out=out)
+    torch.cuda.synchronize()
+    est.set_option("pipeline", 1)
+    est.profile_begin(K)
+    for i in range(K):
+        est.estimate_area(resident[i % len(resident)], lp_nofb, uids, out=out)
+    torch.cuda.synchronize()
+    kt = est.profile_end()
+    G = 10 if K % 10 == 0 else 1
+    graphs = [est.capture(r, lp, uids, out=out, calls=G) for r in resident]
+    for g in graphs:
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K // G):
+        graphs[i % len(graphs)].launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for g in graphs:
+        g.close()
+    lat = []
+    for i in range(min(args.latency_calls, 100)):
+        t1 = time.perf_counter()
+        est.estimate_area(resident[i % len(resident)], lp, uids, out=out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    cnn_ms = kt["strips"]["avg_ms"]
+    flops = B * cnn_flops_per_frame(W, H, kw["n_hstrips"], kw["n_vstrips"])
+    rl = {"kernel": "k_cnn_strips", "bound": "mfma",
+          "achieved": flops / (cnn_ms * 1e-3) / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
+          "unit": "TFLOP/s", "traffic": None}
+    rl["frac"] = rl["achieved"] / rl["peak"]
+    print("# learned: accuracy", file=sys.stderr, flush=True)
+    acc_plain = evaluate.accuracy(est, resident[0], specs, params_plain)
+    acc_learned = evaluate.accuracy(est, resident[0], specs, lp)
+    hard, hard_specs = synth_gpu.render_set(synth.HARD_1080p, synth.HARD_1080p.config_id,
+                                            args.hard_frames, True)
+    hard_plain = evaluate.accuracy(est, hard, hard_specs, params_plain)
+    hard_learned = evaluate.accuracy(est, hard, hard_specs, lp)
+    return {
+        "value": B * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
+        "steps": K, "timing": f"HIP graphs of {G} calls",
+        "scorer": "learned 1-D CNN (BF16 MFMA), handcrafted fallback below 0.5 inlier fraction",
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "kernels": {"k_cnn_strips": {"avg_us": cnn_ms * 1e3},
+                    "k_ransac": {"avg_us": kt["ransac"]["avg_ms"] * 1e3}},
+        "kernel_timing": "learned scorer without fallback, one launch per kernel",
+        "roofline": rl,
+        "accuracy_1080p": {"plain": acc_plain, "learned": acc_learned},
+        "accuracy_hard_1080p": {"plain": hard_plain, "learned": hard_learned,
+                                "frames": args.hard_frames,
+                                "note": "device-rendered: dark rims (edge step 10-25 luma), "
+                                        "border noise sigma 2-12, specular blobs and white "
+                                        "text in the border"},
+    }
+
+
+def mixed_section(args, est, kw):
+    """The uneven batch: 512 frames of 720x576, 1280x720, 1920x1080 and
+    3840x2160 (2:3:4:1) in one captured graph, strip tiles autotuned."""
+    import numpy as np
+    import torch
+    from paper_2210_14771_amd import api, synth
+    if args.mixed_steps <= 0:
+        return None
+    n = synth.MIXED_512.n_frames
+    print(f"# mixed: generating {n} frames", file=sys.stderr, flush=True)
+    frames, specs = synth.make_mixed_batch(n, threads=min(16, os.cpu_count() or 1))
+    sizes = [f.nbytes for f in frames]
+    flat = torch.empty(int(sum(sizes)), dtype=torch.uint8, device="cuda")
+    views, at = [], 0
+    for f in frames:
+        v = flat[at:at + f.nbytes].view(f.shape)
+        v.copy_(torch.from_numpy(f))
+        views.append(v)
+        at += f.nbytes
+    del frames
+    uids = list(range(n))
+    params = api.default_params(**kw)
+    est.set_option("strips_per_group", 0)
+    tuned = est.autotune(views, params, uids, reps=5)
+    out = torch.empty((n, 8), dtype=torch.int32, device="cuda")
+    g = est.capture(views, params, uids, out=out, calls=1)
+    g.launch()
+    torch.cuda.synchronize()
+    K = args.mixed_steps
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g.launch()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    g.close()
+    est.set_option("strips_per_group", 1)
+    g1 = est.capture(views, params, uids, out=out, calls=1)
+    g1.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        g1.launch()
+    torch.cuda.synchronize()
+    untuned = time.perf_counter() - t0
+    g1.close()
+    est.set_option("strips_per_group", 0)
+    algo = sum(strip_bytes_per_frame(s.width, s.height, kw["n_hstrips"], kw["n_vstrips"])
+               for s in specs)
+    return {"workload": "512 frames 720x576 : 1280x720 : 1920x1080 : 3840x2160 = 2:3:4:1, "
+                        "one HIP graph launch per step",
+            "value": n * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
+            "steps": K, "hbm_gbps_algorithmic": algo * K / elapsed / 1e9,
+            "strips_per_group": {f"{w}x{h}": t for (w, h), t in sorted(tuned.items())},
+            "untuned_ms_per_step": untuned / K * 1e3,
+            "frame_bytes": int(sum(sizes))}
 
 
 def cpu_baseline(frames, kw, target_cpu_s: float):
@@ -263,6 +409,13 @@ def main():
         "roofline_other": rl_strips if dominant == "ransac" else rl_ransac,
         "accuracy": acc,
     }
+    print("# learned scorer", file=sys.stderr, flush=True)
+    learned = learned_section(args, est, resident, specs, params, kw, uids, out)
+    if learned is not None:
+        line["learned"] = learned
+    mixed = mixed_section(args, est, kw)
+    if mixed is not None:
+        line["mixed_512"] = mixed
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(frames, kw, args.cpu_seconds)

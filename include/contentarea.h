@@ -288,10 +288,29 @@ void ca_graph_destroy(ca_graph *graph);
                                   internal streams forked from and joined into the
                                   caller's stream (1 = everything on the caller's
                                   stream, the default and the fastest measured) */
+#define CA_OPT_STRIPS_PER_GROUP 7  /* split: strip items per workgroup tile, 1..16, for
+                                      every frame shape; 0 (default) = the autotuned value
+                                      of each shape (ca_autotune), else 1 */
 #define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
                                   per-XCD queues; same results */
+
+/* Autotuner of the split schedule's strip tiles.  A workgroup of the strip
+ * kernel stages the score tables in LDS once and then scores T strip items
+ * in turn (T = 1, 2, 4, 8); frames of each distinct shape in a batch are
+ * launched together with their own T.  For each frame shape of the batch
+ * (enqueued on `stream`, frames as for ca_estimate_area), times `reps`
+ * launches of the strip kernel per candidate T with HIP events and keeps
+ * the fastest for (width, height, n_hstrips, n_vstrips) in the context.
+ * Later calls (and graphs captured later) use it.  Blocking.  Results never
+ * depend on T. */
+int ca_autotune(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
+                int32_t n_frames, const ca_params *params, int32_t reps, void *stream);
+
+/* The tuned T of a frame shape and strip counts (0 if not tuned). */
+int ca_get_tuning(ca_ctx *ctx, int32_t width, int32_t height, int32_t n_hstrips,
+                  int32_t n_vstrips, int32_t *strips_per_group);
 
 /* Set or read an option.  CA_E_INVAL for an unknown option or value. */
 int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value);
@@ -318,6 +337,98 @@ int ca_profile_begin(ca_ctx *ctx, int32_t max_calls);
 
 /* Wait for the timed calls, write their totals and release the events. */
 int ca_profile_end(ca_ctx *ctx, ca_kernel_times *out);
+
+/* ---------------------------------------------------------------- serving --
+ * Continuous batching of many video streams (the per-frame method of
+ * Section 2.2 applied to live footage; temporal filtering with the circle
+ * score as confidence is the extension named in Section 4).
+ *
+ * A stream is opened with its frame shape and is admitted when its frame
+ * ring (ring_slots frames of 3 width height bytes) fits in the server's HBM
+ * budget and fewer than max_streams streams are admitted; otherwise it waits
+ * (first come, first served) until closed streams free memory.  Frames are
+ * submitted per stream in sequence order; each takes a free slot of its
+ * stream's ring (frames wait on the host while the ring is full), is copied
+ * into it on the server's copy stream, and joins the next batch.  ca_server_step
+ * makes progress without blocking: it retires finished batches, admits
+ * streams, starts copies and, while fewer than max_inflight batches are on
+ * the GPU, launches the frames that are ready as one batch.  Frames that
+ * arrive while other batches run are admitted as slots free up, so work of
+ * different arrivals overlaps on the device.
+ *
+ * Per-stream state stays on the device: after each batch a kernel folds every
+ * frame's result, in sequence order, into its stream's filtered circle:
+ * with score q of a valid result and decay lambda = `smooth`,
+ *   w' = lambda w + q,  c' = (lambda w c + q c_frame) / w'  (centre and radius),
+ * and w' = lambda w for an invalid one.  A frame's own result depends only on
+ * its bytes, the parameters and its RNG uid (stream_id << 32 | seq mod 2^32);
+ * the filtered circle only on its stream's earlier frames: both are the same
+ * whatever else is being served. */
+typedef struct ca_server ca_server;
+
+typedef struct {
+    int32_t max_streams;     /* streams admitted at once, 1 .. 65536 */
+    int32_t ring_slots;      /* frame slots per admitted stream, 1 .. 64 */
+    int32_t max_batch;       /* frames per launched batch, 1 .. 4096 */
+    int32_t max_inflight;    /* batches on the GPU at once, 1 .. 8 */
+    uint64_t hbm_budget;     /* bytes for all admitted streams' frame rings */
+    float smooth;            /* temporal filter decay lambda, [0, 1) */
+    int32_t reserved;
+    ca_params params;        /* per-frame parameters (scorer, fallback, ...) */
+} ca_server_config;
+
+/* One served frame (96 bytes). */
+typedef struct {
+    int32_t stream_id;
+    int32_t filtered_valid;  /* the stream's filtered circle exists (w > 0) */
+    uint64_t seq;
+    ca_result result;        /* this frame's own estimate */
+    float fcx, fcy, fr;      /* the stream's filtered circle after this frame */
+    float fweight;           /* its accumulated confidence w */
+    int64_t t_submit_ns;     /* steady-clock times: submission, */
+    int64_t t_launch_ns;     /*   launch of the frame's batch, */
+    int64_t t_done_ns;       /*   and when ca_server_step saw the batch finished */
+    int32_t batch_size;      /* frames in the frame's batch */
+    int32_t pad;
+} ca_served;
+
+/* Create a server on a context with a learned model if params.scorer asks
+ * for it (ca_set_model first).  Allocates the budget, per-batch buffers and
+ * two HIP streams (default priority).  CA_E_INVAL for a bad config, CA_E_NOMEM. */
+int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **server);
+
+/* Finish all work (blocking) and release everything.  Null is ignored. */
+void ca_server_destroy(ca_server *server);
+
+/* Open stream `stream_id` (>= 0, not open) with frames of width x height
+ * (16 .. CA_MAX_EXTENT each).  *admitted = 1 if its ring was reserved now,
+ * 0 if it waits for memory.  The first stream of a new frame shape makes the
+ * next launches rebuild the server's strip tables (a blocking step).
+ * CA_E_INVAL for a bad shape, a negative or duplicate id, or a ring larger
+ * than the whole budget. */
+int ca_server_open(ca_server *server, int32_t stream_id, int32_t width, int32_t height,
+                   int32_t *admitted);
+
+/* Close a stream: its queued and in-flight frames are still served; its
+ * ring is released after the last one. */
+int ca_server_close(ca_server *server, int32_t stream_id);
+
+/* Submit the next frame of an open stream: `src` holds height rows of
+ * 3 width bytes, `row_stride` bytes apart, in device memory
+ * (src_is_device = 1) or pinned host memory (0).  It must stay unchanged
+ * until the frame is served.  `seq` must increase per stream. */
+int ca_server_submit(ca_server *server, int32_t stream_id, uint64_t seq, const uint8_t *src,
+                     int64_t row_stride, int32_t src_is_device);
+
+/* Make progress (never blocks on the GPU); write up to max_out served frames
+ * to `out` (host) in completion order, their count to *n_out.  Served frames
+ * beyond max_out are kept for the next call. */
+int ca_server_step(ca_server *server, ca_served *out, int32_t max_out, int32_t *n_out);
+
+/* Counts: [0] frames submitted, [1] served, [2] queued on the host,
+ * [3] in flight, [4] streams admitted, [5] streams waiting, [6] batches
+ * launched, [7] budget bytes in use. */
+int ca_server_stats(ca_server *server, int64_t out[8]);
 
 /* Static description of a return code. */
 const char *ca_error_string(int code);

@@ -27,6 +27,9 @@ EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
            "ca_graph_destroy", "ca_set_model", "ca_get_model", "ca_set_momentum",
            "ca_cnn_window_logits", "ca_cnn_gradients", "ca_cnn_sgd_step", "ca_selftest_mfma",
+           "ca_autotune", "ca_get_tuning", "ca_server_create", "ca_server_destroy",
+           "ca_server_open", "ca_server_close", "ca_server_submit", "ca_server_step",
+           "ca_server_stats",
            "ca_error_string", "ca_version")
 CA_SCORER_HANDCRAFTED = 0
 CA_SCORER_LEARNED = 1
@@ -40,6 +43,7 @@ CA_OPT_QUEUES = 3
 CA_OPT_GRID = 4
 CA_OPT_SPIN_LIMIT = 5
 CA_OPT_PIPELINE = 6
+CA_OPT_STRIPS_PER_GROUP = 7
 CA_SCHEDULE_SPLIT = 0
 CA_SCHEDULE_FUSED = 1
 
@@ -75,6 +79,20 @@ class AttemptRec(C.Structure):
                 ("i1", C.c_int32), ("i2", C.c_int32), ("inliers", C.c_int32),
                 ("qsum", C.c_uint64), ("cx", C.c_double), ("cy", C.c_double),
                 ("r2", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_streams", C.c_int32), ("ring_slots", C.c_int32), ("max_batch", C.c_int32),
+                ("max_inflight", C.c_int32), ("hbm_budget", C.c_uint64), ("smooth", C.c_float),
+                ("reserved", C.c_int32), ("params", Params)]
+
+
+class Served(C.Structure):
+    _fields_ = [("stream_id", C.c_int32), ("filtered_valid", C.c_int32), ("seq", C.c_uint64),
+                ("result", ResultRec), ("fcx", C.c_float), ("fcy", C.c_float),
+                ("fr", C.c_float), ("fweight", C.c_float), ("t_submit_ns", C.c_int64),
+                ("t_launch_ns", C.c_int64), ("t_done_ns", C.c_int64), ("batch_size", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class KernelTimes(C.Structure):
@@ -128,6 +146,16 @@ def lib() -> C.CDLL:
         L.ca_cnn_gradients.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
         L.ca_cnn_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
         L.ca_selftest_mfma.argtypes = [vp, vp, vp]
+        L.ca_autotune.argtypes = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params), i32, vp]
+        L.ca_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.ca_server_destroy.argtypes = [vp]
+        L.ca_server_destroy.restype = None
+        L.ca_server_open.argtypes = [vp, i32, i32, i32, C.POINTER(C.c_int32)]
+        L.ca_server_close.argtypes = [vp, i32]
+        L.ca_server_submit.argtypes = [vp, i32, C.c_uint64, vp, C.c_int64, i32]
+        L.ca_server_step.argtypes = [vp, vp, i32, C.POINTER(C.c_int32)]
+        L.ca_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.ca_get_tuning.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int32)]
         L.ca_set_option.argtypes = [vp, i32, C.c_int64]
         L.ca_get_option.argtypes = [vp, i32, C.POINTER(C.c_int64)]
         L.ca_device_status.argtypes = [vp]

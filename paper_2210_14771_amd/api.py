@@ -183,7 +183,7 @@ class Estimator:
 
     OPTIONS = {"schedule": N.CA_OPT_SCHEDULE, "lag": N.CA_OPT_LAG, "queues": N.CA_OPT_QUEUES,
                "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT,
-               "pipeline": N.CA_OPT_PIPELINE}
+               "pipeline": N.CA_OPT_PIPELINE, "strips_per_group": N.CA_OPT_STRIPS_PER_GROUP}
 
     def set_option(self, name: str, value: int) -> None:
         """Options: schedule ("split"/"fused" or 0/1), pipeline (sub-batches of a split
@@ -313,6 +313,25 @@ class Estimator:
                                       C.c_void_p(out.data_ptr()), C.c_void_p(s.cuda_stream))
         N.check(rc, "ca_estimate_area")
         return Result(out)
+
+    def autotune(self, frames, params=None, frame_uids=None, reps: int = 5) -> dict:
+        """Tune the strip tile (strip items per workgroup) of every frame shape
+        in the batch; returns {(width, height): T}."""
+        base, descs, n, p, s = self._prep(frames, params, frame_uids, None)
+        N.check(N.lib().ca_autotune(self._ctx, C.c_void_p(base), descs, n, C.byref(p), reps,
+                                    C.c_void_p(s.cuda_stream)), "ca_autotune")
+        out = {}
+        for i in range(n):
+            key = (descs[i].width, descs[i].height)
+            if key not in out:
+                out[key] = self.get_tuning(key[0], key[1], p.n_hstrips, p.n_vstrips)
+        return out
+
+    def get_tuning(self, width: int, height: int, n_hstrips: int, n_vstrips: int) -> int:
+        v = C.c_int32()
+        N.check(N.lib().ca_get_tuning(self._ctx, width, height, n_hstrips, n_vstrips, C.byref(v)),
+                "ca_get_tuning")
+        return int(v.value)
 
     def capture(self, frames, params=None, frame_uids=None, out: torch.Tensor | None = None,
                 calls: int = 1) -> "Graph":

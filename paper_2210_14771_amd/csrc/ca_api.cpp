@@ -5,18 +5,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
 
-#include "ca_cnn.h"
+#include "ca_host.h"
 
-namespace {
-
-using ca::FrameDev;
-using ca::Record;
+namespace cahost {
 
 constexpr double kPi = 3.14159265358979323846;
 
@@ -65,35 +64,6 @@ int score_tables(const ca_params &p, float *sg, int32_t *sg_len, float *st, floa
 
 // --------------------------------------------------------------- plans ----
 
-struct Shape {
-    int32_t W, H;
-};
-
-struct Plan {
-    // cache key
-    std::vector<ca_frame_desc> dims;
-    int32_t n_h = 0, n_v = 0, attempts = 0;
-    double alpha = 0, t_g = 0, t_theta = 0, t_iota = 0;
-    // device buffers (one allocation)
-    void *mem = nullptr;
-    size_t bytes = 0;
-    FrameDev *fd = nullptr;
-    int32_t *strips = nullptr;
-    float *lut = nullptr;
-    ca_point *cand = nullptr;
-    Record *rec = nullptr;
-    uint32_t *ctl = nullptr;    // fused-kernel control words (zero between calls)
-    ca_result *res2 = nullptr;  // handcrafted results of a learned call with fallback
-    // launch facts
-    int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
-    bool rows_aligned = false;  // every row offset a multiple of 16
-    size_t lds = 0;
-    size_t fused_lds = 0;
-    int32_t fused_grid = 0;     // resident workgroups of the fused kernel
-    int32_t pins = 0;           // graphs that replay this plan (never evicted while > 0)
-    uint64_t last_use = 0;
-};
-
 bool same_key(const Plan &pl, const ca_frame_desc *dims, int32_t n, const ca_params &p)
 {
     return pl.n_frames == n && pl.n_h == p.n_hstrips && pl.n_v == p.n_vstrips
@@ -102,56 +72,11 @@ bool same_key(const Plan &pl, const ca_frame_desc *dims, int32_t n, const ca_par
            && std::memcmp(pl.dims.data(), dims, sizeof(ca_frame_desc) * (size_t)n) == 0;
 }
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+}  // namespace cahost
 
-}  // namespace
+using namespace cahost;
 
-struct ca_ctx {
-    int device = 0;
-    size_t budget = 0;
-    size_t used = 0;
-    size_t max_lds = 0;
-    uint64_t tick = 0;
-    std::vector<Plan *> plans;
-    // kernel timing: 4 events per timed call (before strips, between kernels, after select)
-    std::vector<hipEvent_t> prof_events;
-    int32_t prof_capacity = 0;
-    int32_t prof_used = 0;
-    // schedule options (ca_set_option)
-    int64_t schedule = CA_SCHEDULE_SPLIT;
-    int64_t lag = 4;
-    int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
-    int64_t grid = 0;           // 0: resident workgroups from the occupancy query
-    int64_t spin_limit = 1 << 20;
-    int64_t pipeline = 1;       // sub-batches of a split-schedule call (1: no side streams)
-    int n_cu = 0;
-    // side streams of the pipelined split schedule, with their fork/join events
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[2] = {nullptr, nullptr};
-    uint8_t *model = nullptr;   // learned scorer, device block (ca_set_model)
-    float *train = nullptr;     // master weights [kCnnParams], then momentum [kCnnParams]
-    float *partial = nullptr;   // gradient partials [grad_grid][kCnnGradStride]
-    int grad_grid = 0;
-};
-
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            return;
-        ok = prev == dev || hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (ok && prev >= 0)
-            (void)hipSetDevice(prev);
-    }
-};
+namespace cahost {
 
 void free_plan(ca_ctx *ctx, Plan *pl)
 {
@@ -236,6 +161,17 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
         if ((d.byte_offset % 16) != 0 || (d.row_stride % 16) != 0)
             pl->rows_aligned = false;
     }
+    // frames grouped by shape: the strip kernel is launched per shape class
+    std::vector<int32_t> flist;
+    flist.reserve((size_t)n);
+    for (size_t k = 0; k < shapes.size(); ++k) {
+        const int32_t first = (int32_t)flist.size();
+        for (int32_t i = 0; i < n; ++i)
+            if (dims[i].width == shapes[k].W && dims[i].height == shapes[k].H)
+                flist.push_back(i);
+        pl->classes.push_back({shapes[k].W, shapes[k].H, first, (int32_t)flist.size() - first});
+    }
+    pl->shapes = shapes;
     std::vector<float> lut((size_t)CA_SG_CAPACITY + ca::kQtBins + ca::kLumaLevels);
     int32_t sg_len = 0;
     std::vector<float> st(ca::kQtBins), si(ca::kLumaLevels);
@@ -266,7 +202,8 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     const size_t o_rec = align_up(o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
     const size_t o_ctl = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
     const size_t o_res2 = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
-    const size_t total = align_up(o_res2 + sizeof(ca_result) * (size_t)n, 256);
+    const size_t o_flist = align_up(o_res2 + sizeof(ca_result) * (size_t)n, 256);
+    const size_t total = align_up(o_flist + sizeof(int32_t) * (size_t)n, 256);
 
     // evict least recently used unpinned plans until this one fits the budget
     while (ctx->used + total > ctx->budget) {
@@ -299,6 +236,7 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     pl->rec = reinterpret_cast<Record *>(base + o_rec);
     pl->ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
     pl->res2 = reinterpret_cast<ca_result *>(base + o_res2);
+    pl->flist = reinterpret_cast<int32_t *>(base + o_flist);
     // plans are built once per batch shape; a blocking upload keeps them simple
     bool ok = hipMemcpy(pl->fd, fd.data(), sizeof(FrameDev) * (size_t)n, hipMemcpyHostToDevice)
                   == hipSuccess
@@ -307,6 +245,8 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
                      == hipSuccess
               && hipMemcpy(pl->lut, lut.data(), sizeof(float) * lut.size(), hipMemcpyHostToDevice)
                      == hipSuccess
+              && hipMemcpy(pl->flist, flist.data(), sizeof(int32_t) * flist.size(),
+                           hipMemcpyHostToDevice) == hipSuccess
               && hipMemset(pl->ctl, 0, sizeof(uint32_t) * ca::ctl_words(n)) == hipSuccess
               && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
@@ -328,7 +268,7 @@ int get_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params 
         return rc;
     Plan *pl = nullptr;
     for (Plan *c : ctx->plans)
-        if (same_key(*c, dims, n, p)) {
+        if (!c->dynamic && same_key(*c, dims, n, p)) {
             pl = c;
             break;
         }
@@ -343,6 +283,28 @@ int get_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params 
 }
 
 // Enqueue the whole path for one batch on stream `s`.
+int32_t strips_per_group(const ca_ctx *ctx, int32_t W, int32_t H, const ca_params &p)
+{
+    if (ctx->strips_per_group > 0)
+        return (int32_t)ctx->strips_per_group;
+    const auto it = ctx->tuned.find({W, H, p.n_hstrips, p.n_vstrips});
+    return it == ctx->tuned.end() ? 1 : it->second;
+}
+
+// Strip launches of one shape class with T items per workgroup.
+hipError_t launch_class_strips(const ca::StripArgs &base, const Plan *pl,
+                               const Plan::ShapeClass &c, int32_t T, int32_t S, hipStream_t st)
+{
+    ca::StripArgs a = base;
+    a.frame0 = 0;
+    a.frame_list = pl->flist + c.first;
+    a.n_items = c.count * S;
+    a.items_per_group = T;
+    const int32_t groups = (a.n_items + T - 1) / T;
+    a.per_xcd = (groups + 7) / 8;
+    return ca::launch_strips(a, pl->lds, st);
+}
+
 int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
                 ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
                 bool timed)
@@ -362,6 +324,8 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     sa.line_pitch = pl->line_pitch;
     sa.aligned = (pl->rows_aligned && (reinterpret_cast<uintptr_t>(frames) % 16) == 0) ? 1 : 0;
     sa.frame0 = 0;
+    sa.frame_list = nullptr;
+    sa.items_per_group = 1;
 
     ca::RansacArgs ra;
     ra.fd = pl->fd;
@@ -437,6 +401,15 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
             c.per_xcd = a2.per_xcd;
             c.frame0 = f0;
             ok = ca::launch_cnn_strips(c, st) == hipSuccess;
+        } else if (f0 == 0 && f1 == n && !pl->dynamic
+                   && (pl->classes.size() > 1
+                       || strips_per_group(ctx, pl->classes[0].W, pl->classes[0].H, p) != 1)) {
+            // the whole batch: one launch per frame shape, each with its tile
+            ok = true;
+            for (const Plan::ShapeClass &c : pl->classes)
+                ok = ok
+                     && launch_class_strips(sa, pl, c, strips_per_group(ctx, c.W, c.H, p), S, st)
+                            == hipSuccess;
         } else {
             ok = ca::launch_strips(a2, pl->lds, st) == hipSuccess;
         }
@@ -529,7 +502,7 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
                    static_cast<hipStream_t>(stream), true);
 }
 
-}  // namespace
+}  // namespace cahost
 
 struct ca_graph {
     ca_ctx *ctx = nullptr;
@@ -982,6 +955,90 @@ int ca_selftest_mfma(ca_ctx *ctx, float *out, void *stream)
                                                                                        : CA_E_DEVICE;
 }
 
+int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
+                const ca_params *params, int32_t reps, void *stream)
+{
+    if (!ctx || n < 0 || reps < 1 || reps > 1000)
+        return CA_E_INVAL;
+    if (n == 0)
+        return CA_OK;
+    if (!frames || !dims)
+        return CA_E_INVAL;
+    ca_params p;
+    if (params)
+        p = *params;
+    else
+        ca_default_params(&p);
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    Plan *pl = nullptr;
+    int rc = get_plan(ctx, dims, n, p, &pl);
+    if (rc != CA_OK)
+        return rc;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    ca::StripArgs sa;
+    sa.frames = frames;
+    sa.fd = pl->fd;
+    sa.strips = pl->strips;
+    sa.lut = pl->lut;
+    sa.cand = pl->cand;
+    sa.sg_len = pl->sg_len;
+    sa.n_h = p.n_hstrips;
+    sa.n_v = p.n_vstrips;
+    sa.line_pitch = pl->line_pitch;
+    sa.aligned = (pl->rows_aligned && (reinterpret_cast<uintptr_t>(frames) % 16) == 0) ? 1 : 0;
+    sa.frame0 = 0;
+    sa.frame_list = nullptr;
+    sa.items_per_group = 1;
+    sa.n_items = 0;
+    sa.per_xcd = 0;
+    const int32_t S = p.n_hstrips + p.n_vstrips;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return CA_E_DEVICE;
+    }
+    rc = CA_OK;
+    for (const Plan::ShapeClass &c : pl->classes) {
+        int32_t best_t = 1;
+        float best_ms = 0.0f;
+        for (int32_t T : {1, 2, 4, 8}) {
+            bool ok = launch_class_strips(sa, pl, c, T, S, st) == hipSuccess   // warm-up
+                      && hipEventRecord(e0, st) == hipSuccess;
+            for (int32_t r = 0; ok && r < reps; ++r)
+                ok = launch_class_strips(sa, pl, c, T, S, st) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess
+                 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (!ok) {
+                rc = CA_E_DEVICE;
+                break;
+            }
+            if (T == 1 || ms < best_ms) {
+                best_ms = ms;
+                best_t = T;
+            }
+        }
+        if (rc != CA_OK)
+            break;
+        ctx->tuned[{c.W, c.H, p.n_hstrips, p.n_vstrips}] = best_t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int ca_get_tuning(ca_ctx *ctx, int32_t W, int32_t H, int32_t n_h, int32_t n_v, int32_t *out)
+{
+    if (!ctx || !out)
+        return CA_E_INVAL;
+    const auto it = ctx->tuned.find({W, H, n_h, n_v});
+    *out = it == ctx->tuned.end() ? 0 : it->second;
+    return CA_OK;
+}
+
 int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
 {
     if (!ctx)
@@ -1017,6 +1074,11 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
             return CA_E_INVAL;
         ctx->pipeline = value;
         return CA_OK;
+    case CA_OPT_STRIPS_PER_GROUP:
+        if (value < 0 || value > 16)
+            return CA_E_INVAL;
+        ctx->strips_per_group = value;
+        return CA_OK;
     default:
         return CA_E_INVAL;
     }
@@ -1044,6 +1106,9 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value)
         return CA_OK;
     case CA_OPT_PIPELINE:
         *value = ctx->pipeline;
+        return CA_OK;
+    case CA_OPT_STRIPS_PER_GROUP:
+        *value = ctx->strips_per_group;
         return CA_OK;
     default:
         return CA_E_INVAL;

@@ -48,6 +48,8 @@ struct StripArgs {
     int32_t line_pitch;     // bytes per LDS tile row (>= longest line, multiple of 16)
     int32_t aligned;        // every frame row starts 16-byte aligned
     int32_t frame0;         // first frame of this launch (items cover frames frame0 ..)
+    const int32_t *frame_list;  // or the frames of this launch (null: frame0, frame0 + 1, ..)
+    int32_t items_per_group;    // strip items one workgroup takes in turn (tables loaded once)
 };
 
 struct RansacArgs {
@@ -102,6 +104,11 @@ size_t fused_lds_bytes(int sg_len, int line_pitch);
 hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s);
 hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s);
+// Serving: fold each run of a batch's results (one stream's frames, in
+// sequence order: run = (state index, first, end)) into the stream's
+// filtered circle (cx, cy, r, weight); filt[i] = the state after frame i.
+hipError_t launch_stream_update(const ca_result *res, const int4 *runs, int n_runs, float4 *state,
+                                float4 *filt, float decay, hipStream_t s);
 // out[f] = fallback[f] (reason + CA_REASON_FALLBACK) where out[f] has fewer
 // than 3 points or inliers < frac * n_points.
 hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, float frac,

@@ -733,14 +733,22 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
     // so workgroup b runs on XCD b % 8; give each XCD a contiguous slice of
     // (frame, strip) items so one frame's strips share that XCD's L2.
+    // A workgroup takes items_per_group consecutive items (a strip tile):
+    // the score tables are staged in LDS once for all of them.
     const int b = blockIdx.x;
-    const int item = (b & 7) * a.per_xcd + (b >> 3);
-    if (item >= a.n_items)
+    const int first = ((b & 7) * a.per_xcd + (b >> 3)) * a.items_per_group;
+    if (first >= a.n_items)
         return;
     load_tables(a, smem);
     const int S = a.n_h + a.n_v;
     const StripLds c = carve_strip_lds(smem, a.sg_len, s_scan, s_best);
-    strip_work(a, c, a.frame0 + item / S, item % S);
+    for (int j = 0; j < a.items_per_group; ++j) {
+        const int item = first + j;
+        if (item >= a.n_items)
+            break;
+        const int k = item / S;
+        strip_work(a, c, a.frame_list ? a.frame_list[k] : a.frame0 + k, item % S);
+    }
 }
 
 // RANSAC groups of frames frame0 .. frame0 + gridDim.y - 1; the last group
@@ -899,6 +907,34 @@ __global__ __launch_bounds__(kBlock) void k_fallback(ca_result *out, const ca_re
     }
 }
 
+// Temporal filter of the serving loop: w' = decay w + q, c' = (decay w c +
+// q c_frame) / w' for a valid result of score q; w' = decay w otherwise.
+__global__ __launch_bounds__(kBlock) void k_stream_update(const ca_result *res, const int4 *runs,
+                                                          int n_runs, float4 *state, float4 *filt,
+                                                          float decay)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n_runs)
+        return;
+    const int4 run = runs[r];
+    float4 st = state[run.x];
+    for (int i = run.y; i < run.z; ++i) {
+        const ca_result q = res[i];
+        const float w = decay * st.w;
+        if (q.valid && q.score > 0.0f) {
+            const float wn = w + q.score;
+            st.x = (w * st.x + q.score * q.cx) / wn;
+            st.y = (w * st.y + q.score * q.cy) / wn;
+            st.z = (w * st.z + q.score * q.r) / wn;
+            st.w = wn;
+        } else {
+            st.w = w;
+        }
+        filt[i] = st;
+    }
+    state[run.x] = st;
+}
+
 }  // namespace
 
 size_t strip_lds_bytes(int sg_len, int line_pitch)
@@ -945,6 +981,16 @@ hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, flo
         return hipSuccess;
     hipLaunchKernelGGL(k_fallback, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, out,
                        fallback, n, frac);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_update(const ca_result *res, const int4 *runs, int n_runs, float4 *state,
+                                float4 *filt, float decay, hipStream_t s)
+{
+    if (n_runs <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_stream_update, dim3((n_runs + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       res, runs, n_runs, state, filt, decay);
     return hipGetLastError();
 }
 

@@ -330,6 +330,40 @@ def smooth_grids(rng: np.random.Generator, spec: FrameSpec):
     return base, fine, chroma, tint
 
 
+# Uneven batch: 512 frames of four resolutions in ratio 2 : 3 : 4 : 1 with the
+# headline distributions, shapes interleaved by a seeded permutation.
+MIXED_512 = Workload(3, 1920, 1080, 512, (60.0, 25.0, 10.0), (2.0, 8.0), (1.0, 3.0), (0.0, 0.4),
+                     None, 32, 32, 1024)
+MIXED_SHAPES = ((720, 576, 2), (1280, 720, 3), (1920, 1080, 4), (3840, 2160, 1))
+WORKLOADS[3] = MIXED_512
+
+
+def mixed_shapes(n: int = 512) -> list[tuple[int, int]]:
+    """(width, height) of frames 0 .. n-1 of the uneven batch."""
+    total = sum(k for _, _, k in MIXED_SHAPES)
+    counts = [n * k // total for _, _, k in MIXED_SHAPES]
+    counts[2] += n - sum(counts)          # the remainder goes to 1080p
+    shapes = [(w, h) for (w, h, _), c in zip(MIXED_SHAPES, counts) for _ in range(c)]
+    order = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 3])).permutation(n)
+    return [shapes[i] for i in order]
+
+
+def make_mixed_batch(n: int = 512, threads: int = 1):
+    """Frames and specs of the uneven batch (a list: the shapes differ)."""
+    shapes = mixed_shapes(n)
+
+    def one(i):
+        return make_frame(MIXED_512, i, *shapes[i])
+
+    if threads > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(threads) as ex:
+            out = list(ex.map(one, range(n)))
+    else:
+        out = [one(i) for i in range(n)]
+    return [f for f, _ in out], [s for _, s in out]
+
+
 # Hard 1080p frames: the headline mix with border noise sigma up to 12 and the
 # distractors above.
 HARD_1080p = Workload(4, 1920, 1080, 64, (60.0, 25.0, 10.0), (2.0, 12.0), (1.0, 3.0), (0.0, 0.4),

@@ -9,7 +9,10 @@ edge label of the ground-truth circle, and runs the library's own forward,
 backward and SGD kernels (ca_cnn_gradients, ca_cnn_sgd_step).  Nothing of
 the step runs on the host except drawing the frames' parameters.
 
-    python -m paper_2210_14771_amd.train_scorer --steps 3125 --out paper_2210_14771_amd/models
+    python -m paper_2210_14771_amd.train_scorer --out paper_2210_14771_amd/models
+
+(the committed model: these defaults, 3125 steps of 64 frames = 200,000
+frames, 83 s on one MI355X; its log is models/scorer_1d_training.json).
 """
 from __future__ import annotations
 
@@ -28,13 +31,17 @@ MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
 MODEL_FILE = "scorer_1d.npy"
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-normal weights, zero biases, in model-file order (float32)."""
+def init_params(seed: int, out_bias: float = -4.0) -> np.ndarray:
+    """Weights and biases uniform in +-1/sqrt(fan_in), in model-file order
+    (float32); the output bias starts at `out_bias` (edge pixels are rare,
+    so the network starts by predicting a small probability everywhere)."""
     rng = np.random.default_rng(seed)
     parts = []
     for ci, co, k in LAYERS:
-        parts.append((rng.standard_normal(co * ci * k) * math.sqrt(2.0 / (ci * k))).astype(np.float32))
-        parts.append(np.zeros(co, dtype=np.float32))
+        b = 1.0 / math.sqrt(ci * k)
+        parts.append(rng.uniform(-b, b, co * ci * k).astype(np.float32))
+        parts.append(rng.uniform(-b, b, co).astype(np.float32))
+    parts[-1][:] = out_bias
     return np.concatenate(parts)
 
 
@@ -90,8 +97,8 @@ class Batch:
 
 
 def train(steps: int = 3125, frames_per_step: int = 64, strips_per_frame: int = 16,
-          lr: float = 0.5, momentum: float = 0.9, warmup: int = 100, hard_frac: float = 0.5,
-          edge_boost: float = 0.0, seed: int = 0, valid_every: int = 100, valid_frames: int = 128,
+          lr: float = 0.05, momentum: float = 0.9, warmup: int = 100, hard_frac: float = 0.5,
+          edge_boost: float = 0.0, seed: int = 0, valid_every: int = 50, valid_frames: int = 128,
           log=print, est: api.Estimator | None = None):
     """Returns (best master weights, log dict)."""
     import torch
@@ -147,12 +154,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3125)
     ap.add_argument("--frames-per-step", type=int, default=64)
     ap.add_argument("--strips-per-frame", type=int, default=16)
-    ap.add_argument("--lr", type=float, default=0.5)
+    ap.add_argument("--lr", type=float, default=0.05)
     ap.add_argument("--momentum", type=float, default=0.9)
     ap.add_argument("--hard-frac", type=float, default=0.5)
     ap.add_argument("--edge-boost", type=float, default=0.0)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--valid-every", type=int, default=100)
+    ap.add_argument("--valid-every", type=int, default=50)
     ap.add_argument("--out", default=MODEL_DIR)
     a = ap.parse_args()
     params, info = train(a.steps, a.frames_per_step, a.strips_per_frame, a.lr, a.momentum,

@@ -1,0 +1,101 @@
+"""The trained learned scorer against the handcrafted one on the same MI355X:
+the fallback rule, determinism of learned calls, and the accuracy gain on
+hard frames (low-contrast rims, strong border noise, specular blobs, text
+in the border) and on the headline 1080p mix."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2210_14771_amd import api, evaluate, synth, synth_gpu, train_scorer
+
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+MODEL = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE)
+KW = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+# frames of the hard evaluation set (seed stream of the hard workload; the
+# training and validation frames come from other streams)
+N_HARD = 96
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def est(torch_dev):
+    if not os.path.exists(MODEL):
+        pytest.skip("no trained scorer model")
+    e = api.Estimator(0)
+    e.set_model(train_scorer.load_model())
+    yield e
+    e.close()
+
+
+@pytest.fixture(scope="module")
+def hard(torch_dev):
+    say("rendering hard frames")
+    return synth_gpu.render_set(synth.HARD_1080p, synth.HARD_1080p.config_id, N_HARD, True)
+
+
+def _raw(est, frames, params):
+    import torch
+    r = est.estimate_area(frames, params, list(range(frames.shape[0])))
+    torch.cuda.synchronize()
+    return r.raw.cpu().numpy()
+
+
+def test_fallback_selects_per_frame_by_inlier_fraction(torch_dev, est, hard):
+    frames, _ = hard
+    frames = frames[:32]
+    learned = _raw(est, frames, api.default_params(**KW, scorer=1))
+    plain = _raw(est, frames, api.default_params(**KW))
+    for frac in (0.5, 0.8):
+        mixed = _raw(est, frames, api.default_params(**KW, scorer=1, fallback_inlier_frac=frac))
+        for i in range(len(frames)):
+            inl, npts = learned[i, 4], learned[i, 5]
+            if npts < 3 or np.float32(inl) < np.float32(frac) * np.float32(npts):
+                want = plain[i].copy()
+                want[7] += 256
+            else:
+                want = learned[i]
+            np.testing.assert_array_equal(mixed[i], want, err_msg=f"frame {i} frac {frac}")
+    # frac 0 is no fallback
+    np.testing.assert_array_equal(
+        _raw(est, frames, api.default_params(**KW, scorer=1, fallback_inlier_frac=0.0)), learned)
+
+
+def test_learned_calls_are_deterministic(torch_dev, est, hard):
+    frames, _ = hard
+    p = api.default_params(**KW, scorer=1, fallback_inlier_frac=0.5)
+    a = _raw(est, frames[:16], p)
+    b = _raw(est, frames[:16], p)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_learned_scorer_gains_on_hard_frames(torch_dev, est, hard):
+    frames, specs = hard
+    plain = evaluate.accuracy(est, frames, specs, api.default_params(**KW))
+    learned = evaluate.accuracy(est, frames, specs,
+                                api.default_params(**KW, scorer=1, fallback_inlier_frac=0.5))
+    say(f"hard frames: plain {plain}  learned {learned}")
+    assert learned["frac_le_2px"] >= plain["frac_le_2px"] + 0.2
+    assert learned["median_px"] < plain["median_px"]
+
+
+def test_learned_scorer_on_headline_mix(torch_dev, est):
+    import torch
+    wl = synth.HD_1080p
+    frames, specs = synth.make_batch(wl, 32)
+    dev = torch.from_numpy(frames).cuda()
+    plain = evaluate.accuracy(est, dev, specs, api.default_params(**KW))
+    learned = evaluate.accuracy(est, dev, specs,
+                                api.default_params(**KW, scorer=1, fallback_inlier_frac=0.5))
+    say(f"1080p mix: plain {plain}  learned {learned}")
+    assert learned["frac_le_2px"] >= plain["frac_le_2px"]

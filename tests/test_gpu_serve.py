@@ -1,0 +1,131 @@
+"""The serving loop: continuous batching of simulated video streams.  Every
+frame's result equals the batch API's result for the same frame and uid,
+whether the stream is served alone or among 47 others; the per-stream
+temporal filter follows its definition; streams wait for memory and are
+admitted as others close."""
+import numpy as np
+import pytest
+
+from paper_2210_14771_amd import api, serve
+
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def streams(torch_dev):
+    say("rendering 48 streams")
+    return serve.make_streams(48, frames_per_stream=6, duration_s=0.4, seed=1)
+
+
+def _key(rec):
+    return rec["stream"], rec["seq"]
+
+
+def test_results_identical_alone_and_in_the_mix(torch_dev, streams):
+    est = api.Estimator(0)
+    srv = serve.Server(est, serve.server_config(max_batch=64, **KW))
+    mix, wall = serve.run(srv, streams)
+    srv.close()
+    say(f"mix: {serve.latency_summary(mix, wall)}")
+    n_expected = sum(len(s.arrivals) for s in streams)
+    assert len(mix) == n_expected
+    assert max(r["batch"] for r in mix) > 1          # batches did form
+    by = {_key(r): r for r in mix}
+    for sid in (0, 1, 2, 5):                          # 720p, 1080p, 4K, 4K
+        srv = serve.Server(est, serve.server_config(max_batch=64, **KW))
+        alone, _ = serve.run(srv, streams, only={sid})
+        srv.close()
+        assert len(alone) == len(streams[sid].arrivals)
+        for r in alone:
+            m = by[_key(r)]
+            assert r["result"] == m["result"], (sid, r["seq"])
+            assert r["filtered"] == m["filtered"], (sid, r["seq"])
+    est.close()
+
+
+def test_each_result_equals_the_batch_api(torch_dev, streams):
+    torch = torch_dev
+    est = api.Estimator(0)
+    srv = serve.Server(est, serve.server_config(max_batch=32, **KW))
+    got, _ = serve.run(srv, streams[:6], realtime=False)
+    srv.close()
+    for r in got:
+        st = streams[r["stream"]]
+        frame = st.frames[r["seq"] % len(st.frames)]
+        uid = (r["stream"] << 32) | r["seq"]
+        res = est.estimate_area(frame, api.default_params(**KW), [uid])
+        torch.cuda.synchronize()
+        raw = res.raw.cpu().numpy()[0]
+        want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
+        assert r["result"] == want, (r["stream"], r["seq"])
+    est.close()
+
+
+def test_temporal_filter_follows_its_definition(torch_dev, streams):
+    est = api.Estimator(0)
+    decay = np.float32(0.8)
+    srv = serve.Server(est, serve.server_config(max_batch=16, smooth=float(decay), **KW))
+    got, _ = serve.run(srv, streams[:3], realtime=False)
+    srv.close()
+    for sid in range(3):
+        recs = sorted((r for r in got if r["stream"] == sid), key=lambda r: r["seq"])
+        x = y = rr = w = np.float32(0.0)
+        for r in recs:
+            cx, cy, rad, score, _, _, valid, _ = r["result"]
+            wd = decay * w
+            if valid and score > 0:
+                s = np.float32(score)
+                wn = wd + s
+                x = (wd * x + s * np.float32(cx)) / wn
+                y = (wd * y + s * np.float32(cy)) / wn
+                rr = (wd * rr + s * np.float32(rad)) / wn
+                w = wn
+            else:
+                w = wd
+            fv, fx, fy, fr, fw = r["filtered"]
+            assert (fx, fy, fr, fw) == (x, y, rr, w), (sid, r["seq"])
+            assert fv == (1 if w > 0 else 0)
+    est.close()
+
+
+def test_streams_wait_for_memory(torch_dev, streams):
+    est = api.Estimator(0)
+    st = streams[1]                                    # 1080p
+    ring = 2 * ((3 * st.width * st.height + 255) // 256 * 256)
+    srv = serve.Server(est, serve.server_config(hbm_budget=2 * ring, max_batch=8, **KW))
+    ids = [1, 4, 7, 10]                               # four 1080p streams
+    adm = [srv.open(i, st.width, st.height) for i in ids]
+    assert adm == [True, True, False, False]
+    for i in ids:
+        for k in range(3):
+            srv.submit(i, k, streams[i].frames[k])
+    served = []
+    for _ in range(100000):
+        served += [serve.served_record(s) for s in srv.step()]
+        if sum(1 for r in served if r["stream"] in ids[:2]) == 6:
+            break
+    assert srv.stats()["streams_waiting"] == 2
+    assert all(r["stream"] in ids[:2] for r in served)
+    srv.close_stream(1)
+    srv.close_stream(4)
+    for _ in range(100000):
+        served += [serve.served_record(s) for s in srv.step()]
+        if len(served) == 12:
+            break
+    assert len(served) == 12
+    st_ = srv.stats()
+    assert st_["streams_waiting"] == 0 and st_["streams_admitted"] == 2
+    srv.close()
+    est.close()

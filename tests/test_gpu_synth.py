@@ -40,7 +40,8 @@ def test_noise_free_frames_match_cpu_image_model(torch_dev, wl):
         assert d.max() <= 1, (i, d.max())
         assert (d > 0).mean() < 1e-3, (i, (d > 0).mean())
         kinds.add(rc.spec.kind)
-    assert len(kinds) >= 2
+    if wl.mix[2] > 0:
+        assert synth.KIND_NOBORDER in kinds and len(kinds) >= 2
 
 
 def test_windows_equal_crops_of_rendered_frames(torch_dev):
@@ -90,6 +91,7 @@ def test_border_noise_statistics(torch_dev):
         far = rho > s.r + 6 * s.blur_sigma
         b = frames[i][far][:, 0]
         assert abs(b.mean() - 6.0) < 0.15 and abs(b.std() - 2.0) < 0.15, (b.mean(), b.std())
-        inner = rho < s.r - 6 * s.blur_sigma
+        # content pixels away from the clipping limits
+        inner = (rho < s.r - 6 * s.blur_sigma)[..., None] & (quiet[i] > 12) & (quiet[i] < 243)
         resid = (frames[i] - quiet[i])[inner]
         assert abs(resid.std() - np.sqrt(4.0 + 1.0 / 12.0)) < 0.1, resid.std()
