@@ -341,8 +341,11 @@ WORKLOADS[3] = MIXED_512
 def mixed_shapes(n: int = 512) -> list[tuple[int, int]]:
     """(width, height) of frames 0 .. n-1 of the uneven batch."""
     total = sum(k for _, _, k in MIXED_SHAPES)
-    counts = [n * k // total for _, _, k in MIXED_SHAPES]
-    counts[2] += n - sum(counts)          # the remainder goes to 1080p
+    # largest remainder: 102 / 154 / 205 / 51 at n = 512
+    quota = [n * k / total for _, _, k in MIXED_SHAPES]
+    counts = [int(q) for q in quota]
+    for i in sorted(range(len(quota)), key=lambda i: counts[i] - quota[i])[:n - sum(counts)]:
+        counts[i] += 1
     shapes = [(w, h) for (w, h, _), c in zip(MIXED_SHAPES, counts) for _ in range(c)]
     order = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 3])).permutation(n)
     return [shapes[i] for i in order]

@@ -70,6 +70,17 @@ def test_graph_with_autotuned_tiles_equals_single_item_tiles(torch_dev, batch):
         g.launch()
         np.testing.assert_array_equal(_raw(api.Result(out)), ref, err_msg=f"replay {rep}")
     g.close()
+    # the persistent schedule (one kernel drawing strip and RANSAC work
+    # items from per-XCD queues), captured the same way
+    est.set_option("schedule", "fused")
+    g = est.capture(views, params, uids, out=out)
+    for rep in range(2):
+        out.zero_()
+        g.launch()
+        np.testing.assert_array_equal(_raw(api.Result(out)), ref, err_msg=f"fused replay {rep}")
+    g.close()
+    est.device_status()        # raises if a wait hit its guard
+    est.set_option("schedule", "split")
     # every forced tile gives the same candidates
     for t in (2, 8):
         est.set_option("strips_per_group", t)
