@@ -37,7 +37,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU work of the oracle sample")
     ap.add_argument("--batches", type=int, default=2, help="distinct resident batches rotated")
-    ap.add_argument("--schedule", choices=["fused", "split"], default="split")
+    ap.add_argument("--schedule", choices=["auto", "fused", "split"], default="auto",
+                    help="auto: the schedule and strip tiles ca_autotune measures fastest for "
+                         "the batch")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
@@ -67,13 +69,14 @@ def ransac_flops(n_points, attempts: int, refine: int) -> float:
     return float(sum(attempts * n * (refine * 23 + 9) for n in n_points if n >= 3))
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_traffic(kernel: str, source: str = "ca_kernels.hip"):
+    """HBM bytes per launch of `kernel` from its committed rocprofv3 counter
+    summary (profiles/<kernel>_64x1080p_hbm_traffic.md), or None when the
+    kernel source changed since the counters were taken."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2210_14771_amd", "csrc", "ca_kernels.hip")
-    summary = os.path.join(ROOT, "profiles", "k_strips_64x1080p_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2210_14771_amd", "csrc", source)
+    summary = os.path.join(ROOT, "profiles", f"{kernel}_64x1080p_hbm_traffic.md")
     try:
         text = open(summary).read()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -142,7 +145,7 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     flops = B * cnn_flops_per_frame(W, H, kw["n_hstrips"], kw["n_vstrips"])
     rl = {"kernel": "k_cnn_strips", "bound": "mfma",
           "achieved": flops / (cnn_ms * 1e-3) / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
-          "unit": "TFLOP/s", "traffic": None}
+          "unit": "TFLOP/s", "traffic": measured_traffic("k_cnn_strips", "ca_cnn.hip")}
     rl["frac"] = rl["achieved"] / rl["peak"]
     print("# learned: accuracy", file=sys.stderr, flush=True)
     hard, hard_specs = synth_gpu.render_set(synth.HARD_1080p, synth.HARD_1080p.config_id,
@@ -193,20 +196,15 @@ def mixed_section(args, est, kw):
     uids = list(range(n))
     params = api.default_params(**kw)
     est.set_option("strips_per_group", 0)
+    est.set_option("schedule", "auto")
     tuned = est.autotune(views, params, uids, reps=5)
+    chosen = est.last_tuned_schedule
     out = torch.empty((n, 8), dtype=torch.int32, device="cuda")
-    g = est.capture(views, params, uids, out=out, calls=1)
-    g.launch()
-    torch.cuda.synchronize()
     K = args.mixed_steps
-    t0 = time.perf_counter()
-    for _ in range(K):
-        g.launch()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    g.close()
-    def timed(setup):
-        setup()
+
+    def timed(schedule, tiles):
+        est.set_option("schedule", schedule)
+        est.set_option("strips_per_group", tiles)
         g1 = est.capture(views, params, uids, out=out, calls=1)
         g1.launch()
         torch.cuda.synchronize()
@@ -218,10 +216,12 @@ def mixed_section(args, est, kw):
         g1.close()
         return dt
 
-    untuned = timed(lambda: est.set_option("strips_per_group", 1))
-    persistent = timed(lambda: (est.set_option("strips_per_group", 0),
-                                est.set_option("schedule", "fused")))
-    est.set_option("schedule", "split")
+    elapsed = timed("auto", 0)
+    split_t1 = timed("split", 1)
+    split_tuned = timed("split", 0)
+    persistent = timed("fused", 0)
+    est.set_option("schedule", "auto")
+    est.set_option("strips_per_group", 0)
     est.device_status()
     algo = sum(strip_bytes_per_frame(s.width, s.height, kw["n_hstrips"], kw["n_vstrips"])
                for s in specs)
@@ -229,11 +229,13 @@ def mixed_section(args, est, kw):
                         "one HIP graph launch per step",
             "value": n * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
             "steps": K, "hbm_gbps_algorithmic": algo * K / elapsed / 1e9,
-            "strips_per_group": {f"{w}x{h}": t for (w, h), t in sorted(tuned.items())},
-            "untuned_ms_per_step": untuned / K * 1e3,
-            "persistent_ms_per_step": persistent / K * 1e3,
-            "note": "value: split schedule (strip kernel per frame shape with its tuned tile, "
-                    "then RANSAC) in one graph; persistent: the single fused kernel in one graph",
+            "autotuned": {"schedule": chosen,
+                          "strips_per_group": {f"{w}x{h}": t for (w, h), t in sorted(tuned.items())}},
+            "ms_per_step_by_schedule": {"split_tile1": split_t1 / K * 1e3,
+                                        "split_tuned_tiles": split_tuned / K * 1e3,
+                                        "persistent_fused": persistent / K * 1e3},
+            "note": "value: the autotuned configuration in one HIP graph per step; split: strip "
+                    "kernel per frame shape then RANSAC; persistent: one fused kernel",
             "frame_bytes": int(sum(sizes))}
 
 
@@ -297,6 +299,17 @@ def main():
     pipeline = est.get_option("pipeline")
     params = api.default_params(**kw)
     out = torch.empty((B, 8), dtype=torch.int32, device=dev)
+    tuning = None
+    if args.schedule == "auto":
+        print("# autotune", file=sys.stderr, flush=True)
+        tiles = {}
+        for r in resident:
+            tiles = est.autotune(r, params, uids, reps=20)
+        schedule_used = est.last_tuned_schedule or "split"
+        tuning = {"schedule": schedule_used,
+                  "strips_per_group": {f"{w}x{h}": t for (w, h), t in tiles.items()}}
+    else:
+        schedule_used = args.schedule
     print("# warmup", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         est.estimate_area(resident[i % len(resident)], params, uids, out=out)
@@ -305,7 +318,7 @@ def main():
     K = args.steps
     # kernel durations: HIP events recorded by the library around each kernel
     # on the launch stream, with the whole batch in one launch per kernel
-    if args.schedule == "split":
+    if schedule_used == "split":
         est.set_option("pipeline", 1)
     est.profile_begin(K)
     torch.cuda.synchronize()
@@ -358,7 +371,7 @@ def main():
     fps = B * K / elapsed
     algo_bytes = B * strip_bytes_per_frame(W, H, kw["n_hstrips"], kw["n_vstrips"])
     flops = ransac_flops(res["n_points"], kw["ransac_attempts"], params.refine_iters)
-    if args.schedule == "fused":
+    if schedule_used == "fused":
         # one kernel runs the whole path: its HBM position on the strip bytes,
         # and its FP64 position on the RANSAC work, over the same duration
         fused_ms = kt["strips"]["avg_ms"]
@@ -371,7 +384,7 @@ def main():
         kernels = {"k_" + k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]}
                    for k, v in kt.items() if k != "unused"}
         dominant = "strips" if strips_ms >= ransac_ms else "ransac"
-    traffic = measured_traffic("k_strips") if args.schedule == "split" else None
+    traffic = measured_traffic("k_strips") if schedule_used == "split" else None
     rl_strips = {"bound": "hbm", "achieved": algo_bytes / (strips_ms * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "traffic": traffic,
                  "traffic_note": "bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
@@ -412,8 +425,9 @@ def main():
         "timing": f"K steps replayed from HIP graphs of {G} calls; eager calls below",
         "eager_value": B * K / elapsed_eager,
         "eager_ms_per_step": elapsed_eager / K * 1e3,
-        "schedule": args.schedule,
-        "pipeline": pipeline if args.schedule == "split" else None,
+        "schedule": schedule_used,
+        "autotune": tuning,
+        "pipeline": pipeline if schedule_used == "split" else None,
         "kernel_timing": "one launch per kernel for the whole batch (pipeline 1)",
         "kernels": kernels,
         "roofline": roofline,

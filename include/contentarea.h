@@ -279,7 +279,8 @@ int ca_graph_launch(ca_graph *graph, void *stream);
 void ca_graph_destroy(ca_graph *graph);
 
 /* Schedule options of a context (ca_set_option / ca_get_option). */
-#define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_SPLIT (default) or CA_SCHEDULE_FUSED */
+#define CA_OPT_SCHEDULE 1      /* CA_SCHEDULE_AUTO (default), CA_SCHEDULE_SPLIT or
+                                  CA_SCHEDULE_FUSED */
 #define CA_OPT_LAG 2           /* fused: frames between a frame's strip and RANSAC work (4) */
 #define CA_OPT_QUEUES 3        /* fused: work queues 1..8; 0 = 8 for >= 16 frames, else 1 */
 #define CA_OPT_GRID 4          /* fused: workgroups; 0 = as many as fit on the device */
@@ -295,6 +296,8 @@ void ca_graph_destroy(ca_graph *graph);
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
                                   per-XCD queues; same results */
+#define CA_SCHEDULE_AUTO 2     /* per batch the schedule ca_autotune measured faster
+                                  (split when the batch was not tuned) */
 
 /* Autotuner of the split schedule's strip tiles.  A workgroup of the strip
  * kernel stages the score tables in LDS once and then scores T strip items
@@ -303,10 +306,15 @@ void ca_graph_destroy(ca_graph *graph);
  * (enqueued on `stream`, frames as for ca_estimate_area), times `reps`
  * launches of the strip kernel per candidate T with HIP events and keeps
  * the fastest for (width, height, n_hstrips, n_vstrips) in the context.
- * Later calls (and graphs captured later) use it.  Blocking.  Results never
- * depend on T. */
+ * Then (handcrafted scorer) it times `reps` whole calls of the batch under
+ * the split schedule with those tiles and under the persistent fused
+ * schedule, and keeps the faster for this batch (used with
+ * CA_SCHEDULE_AUTO); *schedule_out (may be NULL) receives it.  Later calls
+ * (and graphs captured later) use the results.  Blocking.  Results never
+ * depend on T or on the schedule. */
 int ca_autotune(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
-                int32_t n_frames, const ca_params *params, int32_t reps, void *stream);
+                int32_t n_frames, const ca_params *params, int32_t reps, void *stream,
+                int32_t *schedule_out);
 
 /* The tuned T of a frame shape and strip counts (0 if not tuned). */
 int ca_get_tuning(ca_ctx *ctx, int32_t width, int32_t height, int32_t n_hstrips,

@@ -46,6 +46,7 @@ CA_OPT_PIPELINE = 6
 CA_OPT_STRIPS_PER_GROUP = 7
 CA_SCHEDULE_SPLIT = 0
 CA_SCHEDULE_FUSED = 1
+CA_SCHEDULE_AUTO = 2
 
 
 class FrameDesc(C.Structure):
@@ -146,7 +147,8 @@ def lib() -> C.CDLL:
         L.ca_cnn_gradients.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
         L.ca_cnn_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
         L.ca_selftest_mfma.argtypes = [vp, vp, vp]
-        L.ca_autotune.argtypes = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params), i32, vp]
+        L.ca_autotune.argtypes = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params), i32, vp,
+                                  C.POINTER(C.c_int32)]
         L.ca_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
         L.ca_server_destroy.argtypes = [vp]
         L.ca_server_destroy.restype = None

@@ -186,10 +186,11 @@ class Estimator:
                "pipeline": N.CA_OPT_PIPELINE, "strips_per_group": N.CA_OPT_STRIPS_PER_GROUP}
 
     def set_option(self, name: str, value: int) -> None:
-        """Options: schedule ("split"/"fused" or 0/1), pipeline (sub-batches of a split
+        """Options: schedule ("split"/"fused"/"auto" or 0/1/2), pipeline (sub-batches of a split
         call), lag, queues, grid, spin_limit (fused schedule)."""
         if name == "schedule" and isinstance(value, str):
-            value = {"fused": N.CA_SCHEDULE_FUSED, "split": N.CA_SCHEDULE_SPLIT}[value]
+            value = {"fused": N.CA_SCHEDULE_FUSED, "split": N.CA_SCHEDULE_SPLIT,
+                     "auto": N.CA_SCHEDULE_AUTO}[value]
         N.check(N.lib().ca_set_option(self._ctx, self.OPTIONS[name], int(value)), "ca_set_option")
 
     def get_option(self, name: str) -> int:
@@ -318,13 +319,15 @@ class Estimator:
         """Tune the strip tile (strip items per workgroup) of every frame shape
         in the batch; returns {(width, height): T}."""
         base, descs, n, p, s = self._prep(frames, params, frame_uids, None)
+        sched = C.c_int32(-1)
         N.check(N.lib().ca_autotune(self._ctx, C.c_void_p(base), descs, n, C.byref(p), reps,
-                                    C.c_void_p(s.cuda_stream)), "ca_autotune")
+                                    C.c_void_p(s.cuda_stream), C.byref(sched)), "ca_autotune")
         out = {}
         for i in range(n):
             key = (descs[i].width, descs[i].height)
             if key not in out:
                 out[key] = self.get_tuning(key[0], key[1], p.n_hstrips, p.n_vstrips)
+        self.last_tuned_schedule = {0: "split", 1: "fused"}.get(sched.value)
         return out
 
     def get_tuning(self, width: int, height: int, n_hstrips: int, n_vstrips: int) -> int:

@@ -358,7 +358,10 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     hipEvent_t *ev = nullptr;
     if (timed && ctx->prof_used < ctx->prof_capacity)
         ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
-    if (ctx->schedule == CA_SCHEDULE_FUSED && p.scorer == CA_SCORER_HANDCRAFTED) {
+    const bool fused = ctx->schedule == CA_SCHEDULE_FUSED
+                       || (ctx->schedule == CA_SCHEDULE_AUTO
+                           && pl->tuned_schedule == CA_SCHEDULE_FUSED);
+    if (fused && p.scorer == CA_SCORER_HANDCRAFTED) {
         ca::FusedArgs fa;
         fa.s = sa;
         fa.r = ra;
@@ -400,7 +403,11 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
             c.n_items = a2.n_items;
             c.per_xcd = a2.per_xcd;
             c.frame0 = f0;
-            ok = ca::launch_cnn_strips(c, st) == hipSuccess;
+            if (ctx->cnn_groups_per_xcd == 0)
+                ctx->cnn_groups_per_xcd =
+                    std::max(1, (ctx->n_cu > 0 ? ctx->n_cu : 256) / 8 * ca::cnn_strips_blocks_per_cu());
+            ok = ca::launch_cnn_strips(c, std::min(c.per_xcd, ctx->cnn_groups_per_xcd), st)
+                 == hipSuccess;
         } else if (f0 == 0 && f1 == n && !pl->dynamic
                    && (pl->classes.size() > 1
                        || strips_per_group(ctx, pl->classes[0].W, pl->classes[0].H, p) != 1)) {
@@ -956,7 +963,7 @@ int ca_selftest_mfma(ca_ctx *ctx, float *out, void *stream)
 }
 
 int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n,
-                const ca_params *params, int32_t reps, void *stream)
+                const ca_params *params, int32_t reps, void *stream, int32_t *schedule_out)
 {
     if (!ctx || n < 0 || reps < 1 || reps > 1000)
         return CA_E_INVAL;
@@ -1025,6 +1032,29 @@ int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, i
             break;
         ctx->tuned[{c.W, c.H, p.n_hstrips, p.n_vstrips}] = best_t;
     }
+    // whole calls of this batch: the split schedule (with the tiles just
+    // chosen) against the persistent one; the faster serves CA_SCHEDULE_AUTO
+    if (rc == CA_OK && p.scorer == CA_SCORER_HANDCRAFTED) {
+        const int64_t saved = ctx->schedule;
+        float ms[2] = {0.0f, 0.0f};
+        const int64_t cand[2] = {CA_SCHEDULE_SPLIT, CA_SCHEDULE_FUSED};
+        for (int k = 0; k < 2 && rc == CA_OK; ++k) {
+            ctx->schedule = cand[k];
+            bool ok = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, st, false) == CA_OK
+                      && hipEventRecord(e0, st) == hipSuccess;
+            for (int32_t r = 0; ok && r < reps; ++r)
+                ok = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, st, false) == CA_OK;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess
+                 && hipEventElapsedTime(&ms[k], e0, e1) == hipSuccess;
+            if (!ok)
+                rc = CA_E_DEVICE;
+        }
+        ctx->schedule = saved;
+        if (rc == CA_OK)
+            pl->tuned_schedule = ms[1] < ms[0] ? CA_SCHEDULE_FUSED : CA_SCHEDULE_SPLIT;
+    }
+    if (rc == CA_OK && schedule_out)
+        *schedule_out = pl->tuned_schedule;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
@@ -1045,7 +1075,8 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
         return CA_E_INVAL;
     switch (option) {
     case CA_OPT_SCHEDULE:
-        if (value != CA_SCHEDULE_SPLIT && value != CA_SCHEDULE_FUSED)
+        if (value != CA_SCHEDULE_SPLIT && value != CA_SCHEDULE_FUSED
+            && value != CA_SCHEDULE_AUTO)
             return CA_E_INVAL;
         ctx->schedule = value;
         return CA_OK;

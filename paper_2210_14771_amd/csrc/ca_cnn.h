@@ -13,6 +13,7 @@ constexpr int kCnnOut = kCnnWin - 2 * kCnnHalo;
 constexpr int kCnnGuard = 4;   // zero rows around each activation buffer
 constexpr int kCnnRows = kCnnWin + 2 * kCnnGuard;
 constexpr int kCnnLines = 8;   // lines across a learned strip: pos-3 .. pos+4
+constexpr int kCnnWaveBlock = 128;   // inference workgroup: 2 waves, one window each
 
 // Device model block: bfloat16 GEMM weights W_l[C_out][K_pad] with
 // k = tap * C_in + c (zero padding to K_pad), then float32 biases of layers
@@ -33,17 +34,6 @@ constexpr int kCnnParams = 12273;   // float32 parameters of the model file
 // Gradient accumulators in GEMM layout: W1..W4 as kCnnWElems floats, then
 // biases of layers 1-4 (96), w5 (16), b5, the loss: kCnnGradStride floats.
 constexpr int kCnnGradStride = kCnnWElems + 128;
-
-struct __attribute__((aligned(16))) CnnLds {
-    __bf16 w[kCnnWElems];
-    float fb[128];
-    __bf16 x0[kCnnRows * 24];
-    __bf16 h1[kCnnRows * 16];
-    __bf16 h2[kCnnRows * 32];
-    __bf16 h3[kCnnRows * 32];
-    __bf16 h4[kCnnRows * 16];
-    float z[kCnnWin];
-};
 
 struct CnnStripArgs {
     const uint8_t *frames;
@@ -82,6 +72,10 @@ hipError_t launch_cnn_pack(const float *master, uint8_t *model, hipStream_t s);
 hipError_t launch_mfma_probe(float *out, hipStream_t s);
 hipError_t launch_cnn_windows(const uint8_t *model, const uint8_t *win, const int32_t *range,
                               float *z, int n, hipStream_t s);
-hipError_t launch_cnn_strips(const CnnStripArgs &a, hipStream_t s);
+// Learned candidates; a.per_xcd = items per XCD slice, groups_per_xcd =
+// workgroups per XCD (each takes the slice's items in turn).
+hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s);
+// Resident workgroups of k_cnn_strips per compute unit.
+int cnn_strips_blocks_per_cu();
 
 }  // namespace ca

@@ -105,11 +105,6 @@ __device__ void window_forward(const __bf16 *w, const float *fb, const __bf16 *x
     __syncthreads();
 }
 
-__device__ __forceinline__ void window_forward(CnnLds &s, int lo, int hi)
-{
-    window_forward(s.w, s.fb, s.x0, s.h1, s.h2, s.h3, s.h4, s.z, lo, hi);
-}
-
 // One uint8 window [8][128][3] into the position-major input buffer,
 // zero outside [lo, hi).
 __device__ void load_window(__bf16 *x0, const uint8_t *src, int lo, int hi)
@@ -135,22 +130,206 @@ __device__ void zero_guards(__bf16 *buf, int chans)
     }
 }
 
-// Copy the model into LDS and clear the guard rows of the activation buffers.
-__device__ void load_model(CnnLds &s, const uint8_t *model)
+// --------------------------------------------------- wave-level forward --
+//
+// Inference: one wavefront computes one whole window, with every weight
+// fragment of the four convolutions resident in its registers (the A
+// operands: 25 x 16 bytes per lane) and its own activation buffers in LDS, so
+// the layers need no workgroup barrier.  Each B fragment (activations) is read
+// once per k-step and used for every output-channel tile of the layer; the 1x1
+// layer is folded into the last convolution's epilogue (a sum over the four
+// lane groups holding a position's 16 channels).
+
+constexpr int kWaveBytes = kCnnRows * (24 + 32 + 32) * 2;   // x0, ha, hb of one wave
+
+struct WaveFrag {
+    bf16x8 w1[1][4];
+    bf16x8 w2[2][3];
+    bf16x8 w3[2][5];
+    bf16x8 w4[1][5];
+    float b1[1][4], b2[2][4], b3[2][4], b4[1][4];
+    float w5[4];
+    float b5;
+};
+
+template <int MT, int KS>
+__device__ __forceinline__ void load_frag(bf16x8 (&f)[MT][KS], float (&b)[MT][4], const __bf16 *W,
+                                          const float *bias, int lane)
 {
-    const uint4 *src = reinterpret_cast<const uint4 *>(model);
-    uint4 *dst = reinterpret_cast<uint4 *>(s.w);
-    constexpr int n16 = (kCnnWElems * 2) / 16;
-    for (int i = threadIdx.x; i < n16; i += kBlock)
-        dst[i] = src[i];
-    const float *fsrc = reinterpret_cast<const float *>(model + kCnnWElems * 2);
-    for (int i = threadIdx.x; i < kCnnFloats; i += kBlock)
-        s.fb[i] = fsrc[i];
-    zero_guards(s.x0, 24);
-    zero_guards(s.h1, 16);
-    zero_guards(s.h2, 32);
-    zero_guards(s.h3, 32);
-    zero_guards(s.h4, 16);
+    constexpr int KP = KS * 32;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            f[mt][ks] = *reinterpret_cast<const bf16x8 *>(W + (mt * 16 + (lane & 15)) * KP
+                                                          + 32 * ks + 8 * (lane >> 4));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[mt][j] = bias[mt * 16 + 4 * (lane >> 4) + j];
+    }
+}
+
+__device__ void load_wave_frag(WaveFrag &fr, const uint8_t *model, int lane)
+{
+    const __bf16 *W = reinterpret_cast<const __bf16 *>(model);
+    const float *fb = reinterpret_cast<const float *>(model + kCnnFloatsOff);
+    load_frag<1, 4>(fr.w1, fr.b1, W + kCnnWOff[0], fb + kCnnBOff[0], lane);
+    load_frag<2, 3>(fr.w2, fr.b2, W + kCnnWOff[1], fb + kCnnBOff[1], lane);
+    load_frag<2, 5>(fr.w3, fr.b3, W + kCnnWOff[2], fb + kCnnBOff[2], lane);
+    load_frag<1, 5>(fr.w4, fr.b4, W + kCnnWOff[3], fb + kCnnBOff[3], lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        fr.w5[j] = fb[kCnnW5Off + 4 * (lane >> 4) + j];
+    fr.b5 = fb[kCnnW5Off + 16];
+}
+
+// LDS written by some lanes of the wave and read by others next: keep the
+// compiler from moving memory operations across (the hardware keeps a wave's
+// LDS operations in order).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One convolution layer over the window, all MT output tiles per B fragment.
+template <int CIN, int COUT, int MT, int KS>
+__device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float (&bias)[MT][4],
+                                          const __bf16 *X, __bf16 *Y, int lo, int hi, int lane)
+{
+    const int kq = 8 * (lane >> 4);
+#pragma unroll 2
+    for (int nt = 0; nt < kCnnWin / 16; ++nt) {
+        const int n = nt * 16 + (lane & 15);
+        const __bf16 *b_col = X + (n + kCnnGuard - 2) * CIN + kq;
+        f32x4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(b_col + 32 * ks);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt][ks], bv, acc[mt], 0, 0, 0);
+        }
+        const bool inside = n >= lo && n < hi;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v = acc[mt][j] + bias[mt][j];
+                v = v > 0.0f ? v : 0.0f;
+                o[j] = inside ? to_bf16(v) : to_bf16(0.0f);
+            }
+            *reinterpret_cast<bf16x4 *>(Y + (n + kCnnGuard) * COUT + mt * 16 + 4 * (lane >> 4)) = o;
+        }
+    }
+}
+
+// Last convolution (32 -> 16) with the 1x1 layer folded in: z[n] for the
+// wave's 128 positions, returned to lanes 0..15 one n-tile at a time through
+// `emit(n, z)`.
+template <typename Emit>
+__device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *X, int lo, int hi,
+                                              int lane, Emit emit)
+{
+    const int kq = 8 * (lane >> 4);
+#pragma unroll 2
+    for (int nt = 0; nt < kCnnWin / 16; ++nt) {
+        const int n = nt * 16 + (lane & 15);
+        const __bf16 *b_col = X + (n + kCnnGuard - 2) * 32 + kq;
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 5; ++ks) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(b_col + 32 * ks);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w4[0][ks], bv, acc, 0, 0, 0);
+        }
+        const bool inside = n >= lo && n < hi;
+        float part = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = acc[j] + fr.b4[0][j];
+            v = v > 0.0f ? v : 0.0f;
+            const float h = inside ? (float)to_bf16(v) : 0.0f;
+            part = fmaf(fr.w5[j], h, part);
+        }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (lane < 16)
+            emit(n, fr.b5 + part);
+    }
+}
+
+// Logits of one window whose input rows are in w.x0: all 128 positions, in
+// 8 calls of emit (positions outside the strip carry unspecified values).
+template <typename Emit>
+__device__ __forceinline__ void wave_forward(const WaveFrag &fr, __bf16 *x0, __bf16 *ha, __bf16 *hb,
+                                             int lo, int hi, int lane, Emit emit)
+{
+    wave_sync();
+    wave_conv<24, 16, 1, 4>(fr.w1, fr.b1, x0, ha, lo, hi, lane);
+    wave_sync();
+    wave_conv<16, 32, 2, 3>(fr.w2, fr.b2, ha, hb, lo, hi, lane);
+    wave_sync();
+    wave_conv<32, 32, 2, 5>(fr.w3, fr.b3, hb, ha, lo, hi, lane);
+    wave_sync();
+    wave_conv_out(fr, ha, lo, hi, lane, emit);
+    wave_sync();
+}
+
+// Zero one wave's buffers once: afterwards every row holds a finite value.
+// Guard rows and halo positions only ever feed halo outputs (the receptive
+// field of a central position stays inside the window), so later windows
+// may leave stale finite values there.
+__device__ void wave_clear(__bf16 *x0, int lane)
+{
+    uint4 *p = reinterpret_cast<uint4 *>(x0);
+    for (int i = lane; i < kWaveBytes / 16; i += 64)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Gather one window of a strip into a wave's x0: lane l fills positions 2l and
+// 2l + 1 (24 channels each: 8 lines x RGB, (v - 128) / 64); positions outside
+// the strip are zero.
+__device__ __forceinline__ void wave_gather(__bf16 *x0, const uint8_t *frame, int rs,
+                                            bool horizontal, int pos, int extent, int L,
+                                            int start, int lane)
+{
+    typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int n = 2 * lane + q;
+        const int p = start + n;
+        uint8_t v[24];
+        if (p >= 0 && p < L) {
+#pragma unroll
+            for (int j = 0; j < kCnnLines; ++j) {
+                int across = pos + j - 3;
+                across = across < 0 ? 0 : (across > extent - 1 ? extent - 1 : across);
+                const uint8_t *px = horizontal ? frame + (int64_t)across * rs + 3 * p
+                                               : frame + (int64_t)p * rs + 3 * across;
+                v[3 * j] = px[0];
+                v[3 * j + 1] = px[1];
+                v[3 * j + 2] = px[2];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 24; ++j)
+                v[j] = 128;   // (128 - 128) / 64 = 0
+        }
+        bf16x8v *dst = reinterpret_cast<bf16x8v *>(x0 + (n + kCnnGuard) * 24);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            bf16x8v o;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                o[e] = to_bf16(((float)v[8 * c + e] - 128.0f) * (1.0f / 64.0f));
+            dst[c] = o;
+        }
+    }
 }
 
 // --------------------------------------------------------------- kernels --
@@ -176,106 +355,113 @@ __global__ __launch_bounds__(kBlock) void k_mfma_probe(float *out)
         out[(4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[j];
 }
 
-// Logits of the central positions of uint8 windows [n][8][128][3].
-__global__ __launch_bounds__(kBlock) void k_cnn_windows(const uint8_t *model, const uint8_t *win,
-                                                        const int32_t *range, float *z_out,
-                                                        int n_windows)
+// Logits of the central positions of uint8 windows [n][8][128][3]: one
+// wavefront per window.
+__global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_windows(const uint8_t *model,
+                                                               const uint8_t *win,
+                                                               const int32_t *range, float *z_out,
+                                                               int n_windows)
 {
-    __shared__ CnnLds s;
-    load_model(s, model);
-    for (int wi = blockIdx.x; wi < n_windows; wi += gridDim.x) {
+    extern __shared__ __align__(16) uint8_t cnn_smem[];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __bf16 *x0 = reinterpret_cast<__bf16 *>(cnn_smem + wv * kWaveBytes);
+    __bf16 *ha = x0 + kCnnRows * 24;
+    __bf16 *hb = ha + kCnnRows * 32;
+    WaveFrag fr;
+    load_wave_frag(fr, model, lane);
+    wave_clear(x0, lane);
+    const int waves = gridDim.x * (kCnnWaveBlock / 64);
+    for (int wi = blockIdx.x * (kCnnWaveBlock / 64) + wv; wi < n_windows; wi += waves) {
         const int lo = uniform_int(range[2 * wi]);
         const int hi = uniform_int(range[2 * wi + 1]);
-        load_window(s.x0, win + (int64_t)wi * (kCnnLines * kCnnWin * 3), lo, hi);
-        __syncthreads();
-        window_forward(s, lo, hi);
-        const int t = threadIdx.x;
-        if (t < kCnnOut)
-            z_out[(int64_t)wi * kCnnOut + t] = s.z[t + kCnnHalo];
-        __syncthreads();
+        const uint8_t *src = win + (int64_t)wi * (kCnnLines * kCnnWin * 3);
+        wave_sync();
+        for (int i = lane; i < kCnnLines * kCnnWin * 3; i += 64) {
+            const int line = i / (kCnnWin * 3);
+            const int rem = i - line * (kCnnWin * 3);
+            const int n = rem / 3, ch = rem - 3 * (rem / 3);
+            const float v = (n >= lo && n < hi) ? ((float)src[i] - 128.0f) * (1.0f / 64.0f) : 0.0f;
+            x0[(n + kCnnGuard) * 24 + 3 * line + ch] = to_bf16(v);
+        }
+        wave_forward(fr, x0, ha, hb, lo, hi, lane, [&](int n, float z) {
+            if (n >= kCnnHalo && n < kCnnWin - kCnnHalo)
+                z_out[(int64_t)wi * kCnnOut + n - kCnnHalo] = z;
+        });
     }
 }
 
 // Learned candidates: both half strips of each (frame, strip) item, scored
-// by the network, best pixel of each half (ties: outermost).
-__global__ __launch_bounds__(kBlock) void k_cnn_strips(CnnStripArgs a)
+// by the network, best pixel of each half (ties: outermost).  A workgroup of
+// kCnnWaveBlock / 64 waves takes items in turn (XCD-aware slices); its waves
+// share an item's windows.
+__global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_strips(CnnStripArgs a)
 {
-    __shared__ CnnLds s;
-    __shared__ uint64_t s_best[4];
-    const int b = blockIdx.x;
-    const int item = (b & 7) * a.per_xcd + (b >> 3);
-    if (item >= a.n_items)
+    extern __shared__ __align__(16) uint8_t cnn_smem[];
+    __shared__ uint64_t s_best[kCnnWaveBlock / 64][2];
+    constexpr int kWaves = kCnnWaveBlock / 64;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __bf16 *x0 = reinterpret_cast<__bf16 *>(cnn_smem + wv * kWaveBytes);
+    __bf16 *ha = x0 + kCnnRows * 24;
+    __bf16 *hb = ha + kCnnRows * 32;
+    const int xcd = blockIdx.x & 7;
+    const int per_xcd_groups = gridDim.x >> 3;
+    const int first = xcd * a.per_xcd;
+    const int last = min(first + a.per_xcd, a.n_items);
+    if (first + (int)(blockIdx.x >> 3) >= last)
         return;
-    load_model(s, a.model);
+    WaveFrag fr;
+    load_wave_frag(fr, a.model, lane);
+    wave_clear(x0, lane);
     const int S = a.n_h + a.n_v;
-    const int f = uniform_int(a.frame0 + item / S);
-    const int st = uniform_int(item % S);
-    const FrameDev d = a.fd[f];
-    const uint8_t *frame = a.frames + d.offset;
-    const bool horizontal = st < a.n_h;
-    const int pos = uniform_int(a.strips[d.table + st]);
-    const int L = uniform_int(horizontal ? d.W : d.H);
-    const int extent = horizontal ? d.H : d.W;
-    const int tid = threadIdx.x;
-    uint64_t best[2] = {0, 0};
-    for (int p0 = 0; p0 < L; p0 += kCnnOut) {
-        const int lo = p0 >= kCnnHalo ? 0 : kCnnHalo - p0;
-        const int hi = L - p0 + kCnnHalo < kCnnWin ? L - p0 + kCnnHalo : kCnnWin;
-        // gather: 8 lines x 128 positions x 3 colours
-        for (int i = tid; i < kCnnLines * kCnnWin; i += kBlock) {
-            int line, n;
-            if (horizontal) {
-                line = i / kCnnWin;
-                n = i - line * kCnnWin;
-            } else {
-                n = i / kCnnLines;
-                line = i - n * kCnnLines;
-            }
-            const int p = p0 - kCnnHalo + n;
-            __bf16 *dst = s.x0 + (n + kCnnGuard) * 24 + 3 * line;
-            if (p < 0 || p >= L) {
-                dst[0] = dst[1] = dst[2] = to_bf16(0.0f);
-                continue;
-            }
-            int across = pos + line - 3;
-            across = across < 0 ? 0 : (across > extent - 1 ? extent - 1 : across);
-            const uint8_t *px = horizontal ? frame + (int64_t)across * d.rs + 3 * p
-                                           : frame + (int64_t)p * d.rs + 3 * across;
-            dst[0] = to_bf16(((float)px[0] - 128.0f) * (1.0f / 64.0f));
-            dst[1] = to_bf16(((float)px[1] - 128.0f) * (1.0f / 64.0f));
-            dst[2] = to_bf16(((float)px[2] - 128.0f) * (1.0f / 64.0f));
+    for (int item = first + (int)(blockIdx.x >> 3); item < last; item += per_xcd_groups) {
+        const int f = uniform_int(a.frame0 + item / S);
+        const int st = uniform_int(item % S);
+        const FrameDev d = a.fd[f];
+        const uint8_t *frame = a.frames + d.offset;
+        const bool horizontal = st < a.n_h;
+        const int pos = uniform_int(a.strips[d.table + st]);
+        const int L = uniform_int(horizontal ? d.W : d.H);
+        const int extent = horizontal ? d.H : d.W;
+        const int n_win = (L + kCnnOut - 1) / kCnnOut;
+        uint64_t best[2] = {0, 0};
+        for (int w = wv; w < n_win; w += kWaves) {
+            const int p0 = w * kCnnOut;
+            const int start = p0 - kCnnHalo;
+            const int lo = start >= 0 ? 0 : -start;
+            const int hi = L - start < kCnnWin ? L - start : kCnnWin;
+            wave_sync();
+            wave_gather(x0, frame, d.rs, horizontal, pos, extent, L, start, lane);
+            wave_forward(fr, x0, ha, hb, lo, hi, lane, [&](int n, float z) {
+                const int p = start + n;
+                if (n >= kCnnHalo && n < kCnnWin - kCnnHalo && p < L) {
+                    const float sc = sigmoid(z);
+                    const int half = p < (L >> 1) ? 0 : 1;
+                    const int k = half == 0 ? p : L - 1 - p;
+                    const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
+                                         | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+                    best[half] = best[half] > key ? best[half] : key;
+                }
+            });
         }
-        __syncthreads();
-        window_forward(s, lo, hi);
-        if (tid < kCnnOut) {
-            const int p = p0 + tid;
-            if (p < L) {
-                const float sc = sigmoid(s.z[tid + kCnnHalo]);
-                const int half = p < (L >> 1) ? 0 : 1;
-                const int k = half == 0 ? p : L - 1 - p;
-                const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
-                                     | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
-                best[half] = best[half] > key ? best[half] : key;
-            }
-        }
-        __syncthreads();
-    }
-    // reduce the two keys over the workgroup
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int half = 0; half < 2; ++half) {
-        uint64_t v = best[half];
 #pragma unroll
-        for (int dd = 32; dd >= 1; dd >>= 1) {
-            const uint64_t t = __shfl_xor(v, dd, 64);
-            v = v > t ? v : t;
+        for (int half = 0; half < 2; ++half) {
+            uint64_t v = best[half];
+#pragma unroll
+            for (int dd = 32; dd >= 1; dd >>= 1) {
+                const uint64_t t = __shfl_xor(v, dd, 64);
+                v = v > t ? v : t;
+            }
+            if (lane == 0)
+                s_best[wv][half] = v;
         }
-        if (lane == 0)
-            s_best[wv] = v;
         __syncthreads();
-        if (tid == 0) {
-            uint64_t bb = s_best[0];
-            for (int w2 = 1; w2 < 4; ++w2)
-                bb = bb > s_best[w2] ? bb : s_best[w2];
+        if (threadIdx.x < 2) {
+            const int half = threadIdx.x;
+            uint64_t bb = s_best[0][half];
+            for (int w2 = 1; w2 < kWaves; ++w2)
+                bb = bb > s_best[w2][half] ? bb : s_best[w2][half];
             const int k = (int)(0xFFFFFFFFu - (uint32_t)bb);
             const int i = half == 0 ? k : L - 1 - k;
             ca_point pt;
@@ -669,21 +855,39 @@ hipError_t launch_mfma_probe(float *out, hipStream_t s)
     return hipGetLastError();
 }
 
+constexpr size_t kCnnWaveLds = (size_t)(kCnnWaveBlock / 64) * kWaveBytes;
+
 hipError_t launch_cnn_windows(const uint8_t *model, const uint8_t *win, const int32_t *range,
                               float *z, int n, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
-    const int grid = n < 1024 ? n : 1024;
-    hipLaunchKernelGGL(k_cnn_windows, dim3(grid), dim3(kBlock), 0, s, model, win, range, z, n);
+    const int waves = kCnnWaveBlock / 64;
+    int grid = (n + waves - 1) / waves;
+    grid = grid < 1024 ? grid : 1024;
+    hipLaunchKernelGGL(k_cnn_windows, dim3(grid), dim3(kCnnWaveBlock), kCnnWaveLds, s, model, win,
+                       range, z, n);
     return hipGetLastError();
 }
 
-hipError_t launch_cnn_strips(const CnnStripArgs &a, hipStream_t s)
+int cnn_strips_blocks_per_cu()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cnn_strips, kCnnWaveBlock, kCnnWaveLds)
+            != hipSuccess
+        || b < 1) {
+        (void)hipGetLastError();
+        b = 1;
+    }
+    return b;
+}
+
+hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s)
 {
     if (a.n_items <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_cnn_strips, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_cnn_strips, dim3(8 * groups_per_xcd), dim3(kCnnWaveBlock), kCnnWaveLds, s,
+                       a);
     return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct Plan {
     std::vector<ShapeClass> classes;
     std::vector<Shape> shapes;  // distinct frame shapes; shape k's strips at table k * S
     bool dynamic = false;       // a serving plan: descriptors rewritten per batch, not cached
+    int32_t tuned_schedule = -1; // faster schedule of this batch (ca_autotune), -1 untuned
     // launch facts
     int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
     bool rows_aligned = false;  // every row offset a multiple of 16
@@ -84,7 +85,7 @@ struct ca_ctx {
     int32_t prof_capacity = 0;
     int32_t prof_used = 0;
     // schedule options (ca_set_option)
-    int64_t schedule = CA_SCHEDULE_SPLIT;
+    int64_t schedule = CA_SCHEDULE_AUTO;
     int64_t lag = 4;
     int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
@@ -100,6 +101,7 @@ struct ca_ctx {
     float *partial = nullptr;   // gradient partials [grad_grid][kCnnGradStride]
     int grad_grid = 0;
     int64_t strips_per_group = 0;   // 0: tuned per frame shape
+    int cnn_groups_per_xcd = 0;     // resident learned-strip workgroups per XCD (0: not queried)
     std::map<std::array<int32_t, 4>, int32_t> tuned;   // (W, H, n_h, n_v) -> strip items per group
 };
 

@@ -148,7 +148,8 @@ def make_streams(n_streams: int = 48, frames_per_stream: int = 16, duration_s: f
     return out
 
 
-def run(server: Server, streams, realtime: bool = True, only=None, timeout_s: float = 120.0):
+def run(server: Server, streams, realtime: bool = True, only=None, timeout_s: float = 120.0,
+        progress=None):
     """Submit every stream's frames at their arrival times (or as fast as
     possible), step the server until all are served; returns the served
     records and the wall time.  Raises if the frames are not all served
@@ -169,8 +170,12 @@ def run(server: Server, streams, realtime: bool = True, only=None, timeout_s: fl
     served = []
     t0 = time.perf_counter()
     i = 0
+    next_report = 1.0
     while i < len(events) or len(served) < len(events):
         now = time.perf_counter() - t0
+        if progress is not None and now >= next_report:
+            progress(f"t={now:.1f}s submitted {i} served {len(served)} {server.stats()}")
+            next_report += 1.0
         while i < len(events) and (not realtime or events[i][0] <= now):
             _, sid, k = events[i]
             st = by_id[sid]

@@ -46,7 +46,12 @@ def main():
     ap.add_argument("--max-batch", type=int, default=256)
     ap.add_argument("--budget-gib", type=float, default=4.0)
     a = ap.parse_args()
+    import sys
     import torch
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
     print(f"# rendering {a.streams} streams", flush=True)
     streams = serve.make_streams(a.streams, a.frames_per_stream, a.seconds)
     est = api.Estimator(0)
@@ -63,11 +68,11 @@ def main():
         cfg = serve.server_config(max_batch=a.max_batch, hbm_budget=int(a.budget_gib * (1 << 30)),
                                   **params)
         srv = serve.Server(est, cfg)
-        serve.run(srv, streams, realtime=False, timeout_s=300)      # warm-up: plans, tables
+        serve.run(srv, streams, realtime=False, timeout_s=60, progress=log)   # warm-up
         srv.close()
         srv = serve.Server(est, cfg)
         print(f"# serving ({name})", flush=True)
-        served, wall = serve.run(srv, streams, realtime=True, timeout_s=300)
+        served, wall = serve.run(srv, streams, realtime=True, timeout_s=60, progress=log)
         stats = srv.stats()
         srv.close()
         rec = serve.latency_summary(served, wall)

@@ -60,7 +60,9 @@ def test_graph_with_autotuned_tiles_equals_single_item_tiles(torch_dev, batch):
     est.set_option("strips_per_group", 0)
     say("autotuning")
     tuned = est.autotune(views, params, uids, reps=3)
-    say(f"tuned strip items per workgroup: {tuned}")
+    say(f"tuned strip items per workgroup: {tuned}, schedule {est.last_tuned_schedule}")
+    assert est.last_tuned_schedule in ("split", "fused")
+    assert est.get_option("schedule") == 2            # auto: the graph takes the tuned one
     assert set(tuned) == {(w, h) for w, h, _ in synth.MIXED_SHAPES}
     assert all(t in (1, 2, 4, 8) for t in tuned.values())
     out = torch.empty((N, 8), dtype=torch.int32, device="cuda")
