@@ -115,6 +115,7 @@ struct Batch {                          // one in-flight slot
     ca_result *res_host = nullptr;
     float4 *filt_host = nullptr;
     hipEvent_t done = nullptr;
+    hipEvent_t copied = nullptr;        // the copy stream up to this batch's last copy
     std::vector<Entry> entries;
     int64_t t_launch = 0;
     bool busy = false;
@@ -126,7 +127,6 @@ struct ca_server {
     ca_ctx *ctx = nullptr;
     ca_server_config cfg{};
     hipStream_t compute = nullptr, copy = nullptr;
-    hipEvent_t copied = nullptr;
     uint8_t *arena_mem = nullptr;
     Arena arena;
     float4 *state_dev = nullptr;        // [max_streams]
@@ -140,7 +140,6 @@ struct ca_server {
     std::deque<ca_served> done;         // served, not yet returned
     std::vector<cahost::Shape> shapes;  // every frame shape opened so far
     uint64_t shapes_version = 0;
-    bool copies_pending = false;
     int64_t n_submitted = 0, n_served = 0, n_batches = 0;
 };
 
@@ -193,6 +192,8 @@ void free_batch(Batch &b)
 {
     if (b.done)
         (void)hipEventDestroy(b.done);
+    if (b.copied)
+        (void)hipEventDestroy(b.copied);
     (void)hipFree(b.res_dev);
     (void)hipFree(b.filt_dev);
     (void)hipFree(b.runs_dev);
@@ -237,10 +238,12 @@ int retire(ca_server *s)
 {
     while (!s->inflight.empty()) {
         Batch &b = s->batches[s->inflight.front()];
+        // both streams' work of the batch is observed complete by the host,
+        // so the runtime can reclaim what it holds for each of them
         const hipError_t q = hipEventQuery(b.done);
         if (q == hipErrorNotReady)
             return CA_OK;
-        if (q != hipSuccess)
+        if (q != hipSuccess || hipEventQuery(b.copied) != hipSuccess)
             return CA_E_DEVICE;
         const int64_t t = now_ns();
         for (size_t i = 0; i < b.entries.size(); ++i) {
@@ -306,12 +309,7 @@ int ingest(ca_server *s)
                 return CA_E_DEVICE;
             s->ready.push_back({st, p.seq, slot, p.t_submit});
             ++st->outstanding;
-            s->copies_pending = true;
         }
-    }
-    if (s->copies_pending) {
-        if (hipEventRecord(s->copied, s->copy) != hipSuccess)
-            return CA_E_DEVICE;
     }
     return CA_OK;
 }
@@ -354,13 +352,15 @@ int launch(ca_server *s)
                 b.runs_host[n_runs - 1].z = (int)i + 1;
         }
         const hipStream_t cs = s->compute;
-        if (hipMemcpyAsync(b.plan->fd, b.fd_host, n * sizeof(ca::FrameDev), hipMemcpyHostToDevice,
-                           cs) != hipSuccess
+        // every copy issued so far (this batch's frames included) precedes
+        // b.copied on the copy stream; the batch's kernels wait for it
+        if (hipEventRecord(b.copied, s->copy) != hipSuccess
+            || hipMemcpyAsync(b.plan->fd, b.fd_host, n * sizeof(ca::FrameDev), hipMemcpyHostToDevice,
+                              cs) != hipSuccess
             || hipMemcpyAsync(b.runs_dev, b.runs_host, (size_t)n_runs * sizeof(int4),
                               hipMemcpyHostToDevice, cs) != hipSuccess
-            || (s->copies_pending && hipStreamWaitEvent(cs, s->copied, 0) != hipSuccess))
+            || hipStreamWaitEvent(cs, b.copied, 0) != hipSuccess)
             return CA_E_DEVICE;
-        s->copies_pending = false;
         int rc = cahost::enqueue(s->ctx, b.plan, s->arena_mem, (int32_t)n, s->cfg.params, nullptr,
                                  nullptr, b.res_dev, cs, false);
         if (rc != CA_OK)
@@ -416,7 +416,6 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
     const size_t B = (size_t)cfg->max_batch;
     bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess
               && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess
-              && hipEventCreateWithFlags(&s->copied, hipEventDisableTiming) == hipSuccess
               && hipMalloc(&s->arena_mem, cfg->hbm_budget) == hipSuccess
               && hipMalloc(&s->state_dev, sizeof(float4) * (size_t)cfg->max_streams) == hipSuccess
               && hipMemset(s->state_dev, 0, sizeof(float4) * (size_t)cfg->max_streams)
@@ -430,7 +429,8 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
              && hipHostMalloc(&b.runs_host, B * sizeof(int4)) == hipSuccess
              && hipHostMalloc(&b.res_host, B * sizeof(ca_result)) == hipSuccess
              && hipHostMalloc(&b.filt_host, B * sizeof(float4)) == hipSuccess
-             && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess;
+             && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess
+             && hipEventCreateWithFlags(&b.copied, hipEventDisableTiming) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -464,8 +464,6 @@ void ca_server_destroy(ca_server *s)
         delete kv.second;
     (void)hipFree(s->arena_mem);
     (void)hipFree(s->state_dev);
-    if (s->copied)
-        (void)hipEventDestroy(s->copied);
     if (s->compute)
         (void)hipStreamDestroy(s->compute);
     if (s->copy)
