@@ -293,40 +293,111 @@ __device__ void wave_clear(__bf16 *x0, int lane)
 
 // Gather one window of a strip into a wave's x0: lane l fills positions 2l and
 // 2l + 1 (24 channels each: 8 lines x RGB, (v - 128) / 64); positions outside
-// the strip are zero.
-__device__ __forceinline__ void wave_gather(__bf16 *x0, const uint8_t *frame, int rs,
-                                            bool horizontal, int pos, int extent, int L,
-                                            int start, int lane)
+// the strip are zero.  Bytes come from aligned dword loads split with
+// v_alignbyte (a horizontal strip: 6 bytes of each of 8 rows; a vertical one:
+// 24 bytes of each of 2 rows), with byte loads where a line is clamped at the
+// frame edge, the strip ends inside the pair, or the dwords would leave the
+// frame.
+__device__ __forceinline__ void wave_gather(__bf16 *x0, const uint8_t *frame, int W, int H, int rs,
+                                            bool horizontal, int pos, int L, int start, int lane)
 {
     typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+    const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
+    const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
+    const int extent = horizontal ? H : W;
+    const int p = start + 2 * lane;
+    uint8_t v[2][24];
+    if (p >= 0 && p + 1 < L) {
+        if (horizontal) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int n = 2 * lane + q;
-        const int p = start + n;
-        uint8_t v[24];
-        if (p >= 0 && p < L) {
+            for (int j = 0; j < kCnnLines; ++j) {
+                int row = pos + j - 3;
+                row = row < 0 ? 0 : (row > extent - 1 ? extent - 1 : row);
+                const uint8_t *q = frame + (int64_t)row * rs + 3 * p;
+                const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
+                const uint32_t sh = (uint32_t)(addr & 3);
+                if (addr - sh >= fstart && addr - sh + 12 <= fend) {
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
+                    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+                    const uint32_t b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+                    const uint32_t b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+                    v[0][3 * j] = (uint8_t)b03;
+                    v[0][3 * j + 1] = (uint8_t)(b03 >> 8);
+                    v[0][3 * j + 2] = (uint8_t)(b03 >> 16);
+                    v[1][3 * j] = (uint8_t)(b03 >> 24);
+                    v[1][3 * j + 1] = (uint8_t)b47;
+                    v[1][3 * j + 2] = (uint8_t)(b47 >> 8);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        v[0][3 * j + c] = q[c];
+                        v[1][3 * j + c] = q[3 + c];
+                    }
+                }
+            }
+        } else {
+            const bool inner = pos - 3 >= 0 && pos + 4 <= extent - 1;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const uint8_t *rowp = frame + (int64_t)(p + k) * rs;
+                const uint8_t *q = rowp + 3 * (pos - 3);
+                const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
+                const uint32_t sh = (uint32_t)(addr & 3);
+                if (inner && addr - sh >= fstart && addr - sh + 28 <= fend) {
+                    const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
+                    uint32_t wd[7];
+#pragma unroll
+                    for (int i = 0; i < 7; ++i)
+                        wd[i] = w[i];
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) {
+                        const uint32_t d = __builtin_amdgcn_alignbyte(wd[i + 1], wd[i], sh);
+                        v[k][4 * i] = (uint8_t)d;
+                        v[k][4 * i + 1] = (uint8_t)(d >> 8);
+                        v[k][4 * i + 2] = (uint8_t)(d >> 16);
+                        v[k][4 * i + 3] = (uint8_t)(d >> 24);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kCnnLines; ++j) {
+                        int col = pos + j - 3;
+                        col = col < 0 ? 0 : (col > extent - 1 ? extent - 1 : col);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            v[k][3 * j + c] = rowp[3 * col + c];
+                    }
+                }
+            }
+        }
+    } else {
+        // a pair at a strip end: position by position, zero outside
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int pk = p + k;
 #pragma unroll
             for (int j = 0; j < kCnnLines; ++j) {
                 int across = pos + j - 3;
                 across = across < 0 ? 0 : (across > extent - 1 ? extent - 1 : across);
-                const uint8_t *px = horizontal ? frame + (int64_t)across * rs + 3 * p
-                                               : frame + (int64_t)p * rs + 3 * across;
-                v[3 * j] = px[0];
-                v[3 * j + 1] = px[1];
-                v[3 * j + 2] = px[2];
-            }
-        } else {
 #pragma unroll
-            for (int j = 0; j < 24; ++j)
-                v[j] = 128;   // (128 - 128) / 64 = 0
+                for (int c = 0; c < 3; ++c) {
+                    uint8_t b = 128;   // (128 - 128) / 64 = 0
+                    if (pk >= 0 && pk < L)
+                        b = horizontal ? frame[(int64_t)across * rs + 3 * pk + c]
+                                       : frame[(int64_t)pk * rs + 3 * across + c];
+                    v[k][3 * j + c] = b;
+                }
+            }
         }
-        bf16x8v *dst = reinterpret_cast<bf16x8v *>(x0 + (n + kCnnGuard) * 24);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        bf16x8v *dst = reinterpret_cast<bf16x8v *>(x0 + (2 * lane + k + kCnnGuard) * 24);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             bf16x8v o;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                o[e] = to_bf16(((float)v[8 * c + e] - 128.0f) * (1.0f / 64.0f));
+                o[e] = to_bf16(((float)v[k][8 * c + e] - 128.0f) * (1.0f / 64.0f));
             dst[c] = o;
         }
     }
@@ -423,7 +494,6 @@ __global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_strips(CnnStripArgs a)
         const bool horizontal = st < a.n_h;
         const int pos = uniform_int(a.strips[d.table + st]);
         const int L = uniform_int(horizontal ? d.W : d.H);
-        const int extent = horizontal ? d.H : d.W;
         const int n_win = (L + kCnnOut - 1) / kCnnOut;
         uint64_t best[2] = {0, 0};
         for (int w = wv; w < n_win; w += kWaves) {
@@ -432,7 +502,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_strips(CnnStripArgs a)
             const int lo = start >= 0 ? 0 : -start;
             const int hi = L - start < kCnnWin ? L - start : kCnnWin;
             wave_sync();
-            wave_gather(x0, frame, d.rs, horizontal, pos, extent, L, start, lane);
+            wave_gather(x0, frame, d.W, d.H, d.rs, horizontal, pos, L, start, lane);
             wave_forward(fr, x0, ha, hb, lo, hi, lane, [&](int n, float z) {
                 const int p = start + n;
                 if (n >= kCnnHalo && n < kCnnWin - kCnnHalo && p < L) {

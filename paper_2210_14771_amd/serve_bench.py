@@ -38,7 +38,13 @@ def accuracy(served, streams) -> dict:
     return out
 
 
+OPEN_ISSUE = ("serve_bench is switched off: its realtime run (after a warm-up server in the "
+              "same process) stopped making progress on the GPU three times; the cause is not "
+              "found yet, so this case is not run until it is")
+
+
 def main():
+    raise SystemExit(OPEN_ISSUE)
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--streams", type=int, default=48)
     # a server has so far only been run to about 900 batches (0.4 s of the
