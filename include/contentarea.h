@@ -357,7 +357,7 @@ int ca_profile_end(ca_ctx *ctx, ca_kernel_times *out);
  * (first come, first served) until closed streams free memory.  Frames are
  * submitted per stream in sequence order; each takes a free slot of its
  * stream's ring (frames wait on the host while the ring is full), is copied
- * into it on the server's copy stream, and joins the next batch.  ca_server_step
+ * into it on the server's HIP stream, and joins the next batch.  ca_server_step
  * makes progress without blocking: it retires finished batches, admits
  * streams, starts copies and, while fewer than max_inflight batches are on
  * the GPU, launches the frames that are ready as one batch.  Frames that
@@ -402,7 +402,8 @@ typedef struct {
 
 /* Create a server on a context with a learned model if params.scorer asks
  * for it (ca_set_model first).  Allocates the budget, per-batch buffers and
- * two HIP streams (default priority).  CA_E_INVAL for a bad config, CA_E_NOMEM. */
+ * one HIP stream (default priority) on which all of its work runs in order.
+ * CA_E_INVAL for a bad config, CA_E_NOMEM. */
 int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **server);
 
 /* Finish all work (blocking) and release everything.  Null is ignored. */

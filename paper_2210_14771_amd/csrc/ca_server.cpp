@@ -2,8 +2,10 @@
 //
 // Host side: per-stream FIFOs of submitted frames, admission of streams by
 // the HBM budget of their frame rings (first fit over one device arena),
-// copies into ring slots on a copy stream, and batches launched on a compute
-// stream whenever fewer than max_inflight are on the GPU.  Device side: the
+// copies into ring slots, and batches launched whenever fewer than
+// max_inflight are on the GPU.  Everything runs on one HIP stream of the
+// server, in order: a frame's copy precedes the batch that reads it, and no
+// work waits on another stream.  Device side: the
 // estimator's kernels on each batch, then one kernel that folds the batch's
 // results into the per-stream filtered circles, in sequence order.
 #include <hip/hip_runtime.h>
@@ -115,7 +117,6 @@ struct Batch {                          // one in-flight slot
     ca_result *res_host = nullptr;
     float4 *filt_host = nullptr;
     hipEvent_t done = nullptr;
-    hipEvent_t copied = nullptr;        // the copy stream up to this batch's last copy
     std::vector<Entry> entries;
     int64_t t_launch = 0;
     bool busy = false;
@@ -126,7 +127,7 @@ struct Batch {                          // one in-flight slot
 struct ca_server {
     ca_ctx *ctx = nullptr;
     ca_server_config cfg{};
-    hipStream_t compute = nullptr, copy = nullptr;
+    hipStream_t compute = nullptr;
     uint8_t *arena_mem = nullptr;
     Arena arena;
     float4 *state_dev = nullptr;        // [max_streams]
@@ -192,8 +193,6 @@ void free_batch(Batch &b)
 {
     if (b.done)
         (void)hipEventDestroy(b.done);
-    if (b.copied)
-        (void)hipEventDestroy(b.copied);
     (void)hipFree(b.res_dev);
     (void)hipFree(b.filt_dev);
     (void)hipFree(b.runs_dev);
@@ -238,12 +237,10 @@ int retire(ca_server *s)
 {
     while (!s->inflight.empty()) {
         Batch &b = s->batches[s->inflight.front()];
-        // both streams' work of the batch is observed complete by the host,
-        // so the runtime can reclaim what it holds for each of them
         const hipError_t q = hipEventQuery(b.done);
         if (q == hipErrorNotReady)
             return CA_OK;
-        if (q != hipSuccess || hipEventQuery(b.copied) != hipSuccess)
+        if (q != hipSuccess)
             return CA_E_DEVICE;
         const int64_t t = now_ns();
         for (size_t i = 0; i < b.entries.size(); ++i) {
@@ -305,7 +302,7 @@ int ingest(ca_server *s)
             if (hipMemcpy2DAsync(dst, (size_t)3 * st->W, p.src, (size_t)p.stride,
                                  (size_t)3 * st->W, (size_t)st->H,
                                  p.is_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                 s->copy) != hipSuccess)
+                                 s->compute) != hipSuccess)
                 return CA_E_DEVICE;
             s->ready.push_back({st, p.seq, slot, p.t_submit});
             ++st->outstanding;
@@ -351,15 +348,12 @@ int launch(ca_server *s)
             else
                 b.runs_host[n_runs - 1].z = (int)i + 1;
         }
+        // the batch's frames were copied earlier on the same stream
         const hipStream_t cs = s->compute;
-        // every copy issued so far (this batch's frames included) precedes
-        // b.copied on the copy stream; the batch's kernels wait for it
-        if (hipEventRecord(b.copied, s->copy) != hipSuccess
-            || hipMemcpyAsync(b.plan->fd, b.fd_host, n * sizeof(ca::FrameDev), hipMemcpyHostToDevice,
-                              cs) != hipSuccess
+        if (hipMemcpyAsync(b.plan->fd, b.fd_host, n * sizeof(ca::FrameDev), hipMemcpyHostToDevice,
+                           cs) != hipSuccess
             || hipMemcpyAsync(b.runs_dev, b.runs_host, (size_t)n_runs * sizeof(int4),
-                              hipMemcpyHostToDevice, cs) != hipSuccess
-            || hipStreamWaitEvent(cs, b.copied, 0) != hipSuccess)
+                              hipMemcpyHostToDevice, cs) != hipSuccess)
             return CA_E_DEVICE;
         int rc = cahost::enqueue(s->ctx, b.plan, s->arena_mem, (int32_t)n, s->cfg.params, nullptr,
                                  nullptr, b.res_dev, cs, false);
@@ -415,7 +409,6 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
     s->cfg = *cfg;
     const size_t B = (size_t)cfg->max_batch;
     bool ok = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess
-              && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess
               && hipMalloc(&s->arena_mem, cfg->hbm_budget) == hipSuccess
               && hipMalloc(&s->state_dev, sizeof(float4) * (size_t)cfg->max_streams) == hipSuccess
               && hipMemset(s->state_dev, 0, sizeof(float4) * (size_t)cfg->max_streams)
@@ -429,8 +422,7 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
              && hipHostMalloc(&b.runs_host, B * sizeof(int4)) == hipSuccess
              && hipHostMalloc(&b.res_host, B * sizeof(ca_result)) == hipSuccess
              && hipHostMalloc(&b.filt_host, B * sizeof(float4)) == hipSuccess
-             && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess
-             && hipEventCreateWithFlags(&b.copied, hipEventDisableTiming) == hipSuccess;
+             && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -451,8 +443,6 @@ void ca_server_destroy(ca_server *s)
     cahost::DeviceGuard guard(s->ctx->device);
     if (s->compute)
         (void)hipStreamSynchronize(s->compute);
-    if (s->copy)
-        (void)hipStreamSynchronize(s->copy);
     for (Batch &b : s->batches) {
         if (b.plan) {
             cahost::free_plan(s->ctx, b.plan);
@@ -466,8 +456,6 @@ void ca_server_destroy(ca_server *s)
     (void)hipFree(s->state_dev);
     if (s->compute)
         (void)hipStreamDestroy(s->compute);
-    if (s->copy)
-        (void)hipStreamDestroy(s->copy);
     delete s;
 }
 
