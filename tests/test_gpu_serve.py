@@ -3,16 +3,20 @@ frame's result equals the batch API's result for the same frame and uid,
 whether the stream is served alone or among 47 others; the per-stream
 temporal filter follows its definition; streams wait for memory and are
 admitted as others close."""
+import json
+import os
+
 import numpy as np
 import pytest
 
-from paper_2210_14771_amd import api, serve
+from paper_2210_14771_amd import api, serve, train_scorer
 
 from gpu_helpers import say
 
 pytestmark = pytest.mark.gpu
 
 KW = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+MODEL = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE)
 
 
 @pytest.fixture(scope="module")
@@ -38,10 +42,25 @@ def test_results_identical_alone_and_in_the_mix(torch_dev, streams):
     srv = serve.Server(est, serve.server_config(max_batch=64, **KW))
     mix, wall = serve.run(srv, streams)
     srv.close()
-    say(f"mix: {serve.latency_summary(mix, wall)}")
+    report = {"plain": serve.latency_summary(mix, wall)}
+    say(f"mix: {report['plain']}")
     n_expected = sum(len(s.arrivals) for s in streams)
     assert len(mix) == n_expected
     assert max(r["batch"] for r in mix) > 1          # batches did form
+    # the same arrivals served with the learned scorer (handcrafted fallback)
+    if os.path.exists(MODEL):
+        est.set_model(train_scorer.load_model())
+        srv = serve.Server(est, serve.server_config(max_batch=64, scorer=1,
+                                                    fallback_inlier_frac=0.5, **KW))
+        learned, lwall = serve.run(srv, streams)
+        srv.close()
+        assert len(learned) == n_expected
+        report["learned"] = serve.latency_summary(learned, lwall)
+        say(f"learned: {report['learned']}")
+    if os.environ.get("CA_SERVE_REPORT"):
+        with open(os.environ["CA_SERVE_REPORT"], "w") as f:
+            json.dump(dict(report, streams=len(streams),
+                           arrival_fps=n_expected / 0.4), f, indent=1)
     by = {_key(r): r for r in mix}
     for sid in (0, 1, 2, 5):                          # 720p, 1080p, 4K, 4K
         srv = serve.Server(est, serve.server_config(max_batch=64, **KW))
