@@ -192,39 +192,56 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// One convolution layer over the window, all MT output tiles per B fragment.
+// One convolution layer over the window: groups of kNB position tiles with
+// independent accumulators (their MFMA chains interleave), every output-
+// channel tile per B fragment.
+constexpr int kNB = 4;
+
 template <int CIN, int COUT, int MT, int KS>
 __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float (&bias)[MT][4],
                                           const __bf16 *X, __bf16 *Y, int lo, int hi, int lane)
 {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int kq = 8 * (lane >> 4);
-#pragma unroll 2
-    for (int nt = 0; nt < kCnnWin / 16; ++nt) {
-        const int n = nt * 16 + (lane & 15);
-        const __bf16 *b_col = X + (n + kCnnGuard - 2) * CIN + kq;
-        f32x4 acc[MT];
+#pragma unroll 1
+    for (int g = 0; g < kCnnWin / 16 / kNB; ++g) {
+        const int n0 = g * kNB * 16 + (lane & 15);
+        const __bf16 *b0 = X + (n0 + kCnnGuard - 2) * CIN + kq;
+        f32x4 acc[kNB][MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(b_col + 32 * ks);
+        for (int t = 0; t < kNB; ++t)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt][ks], bv, acc[mt], 0, 0, 0);
+                acc[t][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8 bv[kNB];
+#pragma unroll
+            for (int t = 0; t < kNB; ++t)
+                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * CIN + 32 * ks);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int t = 0; t < kNB; ++t)
+                    acc[t][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt][ks], bv[t],
+                                                                          acc[t][mt], 0, 0, 0);
         }
-        const bool inside = n >= lo && n < hi;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            bf16x4 o;
+        for (int t = 0; t < kNB; ++t) {
+            const int n = n0 + 16 * t;
+            const bool inside = n >= lo && n < hi;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float v = acc[mt][j] + bias[mt][j];
-                v = v > 0.0f ? v : 0.0f;
-                o[j] = inside ? to_bf16(v) : to_bf16(0.0f);
+            for (int mt = 0; mt < MT; ++mt) {
+                bf16x4 o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v = acc[t][mt][j] + bias[mt][j];
+                    v = v > 0.0f ? v : 0.0f;
+                    o[j] = to_bf16(inside ? v : 0.0f);
+                }
+                *reinterpret_cast<bf16x4 *>(Y + (n + kCnnGuard) * COUT + mt * 16 + 4 * (lane >> 4)) =
+                    o;
             }
-            *reinterpret_cast<bf16x4 *>(Y + (n + kCnnGuard) * COUT + mt * 16 + 4 * (lane >> 4)) = o;
         }
     }
 }
@@ -237,29 +254,42 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
                                               int lane, Emit emit)
 {
     const int kq = 8 * (lane >> 4);
-#pragma unroll 2
-    for (int nt = 0; nt < kCnnWin / 16; ++nt) {
-        const int n = nt * 16 + (lane & 15);
-        const __bf16 *b_col = X + (n + kCnnGuard - 2) * 32 + kq;
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+    for (int g = 0; g < kCnnWin / 16 / kNB; ++g) {
+        const int n0 = g * kNB * 16 + (lane & 15);
+        const __bf16 *b0 = X + (n0 + kCnnGuard - 2) * 32 + kq;
+        f32x4 acc[kNB];
+#pragma unroll
+        for (int t = 0; t < kNB; ++t)
+            acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < 5; ++ks) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(b_col + 32 * ks);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w4[0][ks], bv, acc, 0, 0, 0);
-        }
-        const bool inside = n >= lo && n < hi;
-        float part = 0.0f;
+            bf16x8 bv[kNB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float v = acc[j] + fr.b4[0][j];
-            v = v > 0.0f ? v : 0.0f;
-            const float h = inside ? (float)to_bf16(v) : 0.0f;
-            part = fmaf(fr.w5[j], h, part);
+            for (int t = 0; t < kNB; ++t)
+                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * 32 + 32 * ks);
+#pragma unroll
+            for (int t = 0; t < kNB; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w4[0][ks], bv[t], acc[t], 0, 0,
+                                                                 0);
         }
-        part += __shfl_xor(part, 16, 64);
-        part += __shfl_xor(part, 32, 64);
-        if (lane < 16)
-            emit(n, fr.b5 + part);
+#pragma unroll
+        for (int t = 0; t < kNB; ++t) {
+            const int n = n0 + 16 * t;
+            const bool inside = n >= lo && n < hi;
+            float part = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v = acc[t][j] + fr.b4[0][j];
+                v = v > 0.0f ? v : 0.0f;
+                const float h = inside ? (float)to_bf16(v) : 0.0f;
+                part = fmaf(fr.w5[j], h, part);
+            }
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            if (lane < 16)
+                emit(n, fr.b5 + part);
+        }
     }
 }
 
@@ -293,114 +323,107 @@ __device__ void wave_clear(__bf16 *x0, int lane)
 
 // Gather one window of a strip into a wave's x0: lane l fills positions 2l and
 // 2l + 1 (24 channels each: 8 lines x RGB, (v - 128) / 64); positions outside
-// the strip are zero.  Bytes come from aligned dword loads split with
-// v_alignbyte (a horizontal strip: 6 bytes of each of 8 rows; a vertical one:
-// 24 bytes of each of 2 rows), with byte loads where a line is clamped at the
-// frame edge, the strip ends inside the pair, or the dwords would leave the
-// frame.
+// the strip are zero.  Where the pair lies inside the strip and every dword
+// touched lies inside the frame (decided once per lane), bytes come from
+// aligned dword loads split with v_alignbyte (a horizontal strip: 6 bytes of
+// each of 8 rows; a vertical one: 24 bytes of each of 2 rows); elsewhere
+// (strip ends, clamped lines, frame edges) from byte loads.
+__device__ __forceinline__ void store_row24(__bf16 *row, const uint32_t (&u)[6])
+{
+    typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+    bf16x8v *dst = reinterpret_cast<bf16x8v *>(row);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        bf16x8v o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * c + e;
+            const float b = (float)((u[k >> 2] >> (8 * (k & 3))) & 0xFFu);
+            o[e] = to_bf16(fmaf(b, 1.0f / 64.0f, -2.0f));   // exact: (b - 128) / 64
+        }
+        dst[c] = o;
+    }
+}
+
 __device__ __forceinline__ void wave_gather(__bf16 *x0, const uint8_t *frame, int W, int H, int rs,
                                             bool horizontal, int pos, int L, int start, int lane)
 {
-    typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
-    const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
-    const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
-    const int extent = horizontal ? H : W;
     const int p = start + 2 * lane;
-    uint8_t v[2][24];
-    if (p >= 0 && p + 1 < L) {
+    const int extent = horizontal ? H : W;
+    // every dword window below stays inside the frame: horizontal, 3p - 3 >= 0
+    // and 3p + 12 <= 3W; vertical, 3(pos - 3) - 3 >= 0 and 3(pos - 3) + 28 <= 3W
+    const bool fast = p >= 0 && p + 1 < L
+                      && (horizontal ? (p >= 1 && p <= W - 4) : (pos >= 4 && pos <= W - 7));
+    uint32_t u[2][6];
+    if (fast) {
         if (horizontal) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int i = 0; i < 6; ++i)
+                    u[k][i] = 0;
 #pragma unroll
             for (int j = 0; j < kCnnLines; ++j) {
                 int row = pos + j - 3;
                 row = row < 0 ? 0 : (row > extent - 1 ? extent - 1 : row);
                 const uint8_t *q = frame + (int64_t)row * rs + 3 * p;
-                const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
-                const uint32_t sh = (uint32_t)(addr & 3);
-                if (addr - sh >= fstart && addr - sh + 12 <= fend) {
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
-                    const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-                    const uint32_t b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
-                    const uint32_t b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
-                    v[0][3 * j] = (uint8_t)b03;
-                    v[0][3 * j + 1] = (uint8_t)(b03 >> 8);
-                    v[0][3 * j + 2] = (uint8_t)(b03 >> 16);
-                    v[1][3 * j] = (uint8_t)(b03 >> 24);
-                    v[1][3 * j + 1] = (uint8_t)b47;
-                    v[1][3 * j + 2] = (uint8_t)(b47 >> 8);
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        v[0][3 * j + c] = q[c];
-                        v[1][3 * j + c] = q[3 + c];
-                    }
-                }
+                const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(q) & 3);
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
+                const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+                const uint32_t b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+                const uint32_t b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+                // bytes 3j .. 3j + 2 of each position's 24
+                const uint32_t p0 = b03 & 0xFFFFFFu;
+                const uint32_t p1 = (b03 >> 24) | ((b47 & 0xFFFFu) << 8);
+                const int k = 3 * j;
+                u[0][k >> 2] |= p0 << (8 * (k & 3));
+                if ((k & 3) > 1)
+                    u[0][(k >> 2) + 1] |= p0 >> (32 - 8 * (k & 3));
+                u[1][k >> 2] |= p1 << (8 * (k & 3));
+                if ((k & 3) > 1)
+                    u[1][(k >> 2) + 1] |= p1 >> (32 - 8 * (k & 3));
             }
         } else {
-            const bool inner = pos - 3 >= 0 && pos + 4 <= extent - 1;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                const uint8_t *rowp = frame + (int64_t)(p + k) * rs;
-                const uint8_t *q = rowp + 3 * (pos - 3);
-                const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
-                const uint32_t sh = (uint32_t)(addr & 3);
-                if (inner && addr - sh >= fstart && addr - sh + 28 <= fend) {
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
-                    uint32_t wd[7];
+                const uint8_t *q = frame + (int64_t)(p + k) * rs + 3 * (pos - 3);
+                const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(q) & 3);
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(q - sh);
+                uint32_t wd[7];
 #pragma unroll
-                    for (int i = 0; i < 7; ++i)
-                        wd[i] = w[i];
+                for (int i = 0; i < 7; ++i)
+                    wd[i] = w[i];
 #pragma unroll
-                    for (int i = 0; i < 6; ++i) {
-                        const uint32_t d = __builtin_amdgcn_alignbyte(wd[i + 1], wd[i], sh);
-                        v[k][4 * i] = (uint8_t)d;
-                        v[k][4 * i + 1] = (uint8_t)(d >> 8);
-                        v[k][4 * i + 2] = (uint8_t)(d >> 16);
-                        v[k][4 * i + 3] = (uint8_t)(d >> 24);
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < kCnnLines; ++j) {
-                        int col = pos + j - 3;
-                        col = col < 0 ? 0 : (col > extent - 1 ? extent - 1 : col);
-#pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            v[k][3 * j + c] = rowp[3 * col + c];
-                    }
-                }
+                for (int i = 0; i < 6; ++i)
+                    u[k][i] = __builtin_amdgcn_alignbyte(wd[i + 1], wd[i], sh);
             }
         }
     } else {
-        // a pair at a strip end: position by position, zero outside
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int pk = p + k;
 #pragma unroll
-            for (int j = 0; j < kCnnLines; ++j) {
-                int across = pos + j - 3;
-                across = across < 0 ? 0 : (across > extent - 1 ? extent - 1 : across);
+            for (int i = 0; i < 6; ++i)
+                u[k][i] = 0x80808080u;   // (128 - 128) / 64 = 0
+            if (pk >= 0 && pk < L) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    uint8_t b = 128;   // (128 - 128) / 64 = 0
-                    if (pk >= 0 && pk < L)
-                        b = horizontal ? frame[(int64_t)across * rs + 3 * pk + c]
-                                       : frame[(int64_t)pk * rs + 3 * across + c];
-                    v[k][3 * j + c] = b;
+                for (int j = 0; j < kCnnLines; ++j) {
+                    int across = pos + j - 3;
+                    across = across < 0 ? 0 : (across > extent - 1 ? extent - 1 : across);
+                    const uint8_t *px = horizontal ? frame + (int64_t)across * rs + 3 * pk
+                                                   : frame + (int64_t)pk * rs + 3 * across;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int b = 3 * j + c;
+                        u[k][b >> 2] = (u[k][b >> 2] & ~(0xFFu << (8 * (b & 3))))
+                                       | ((uint32_t)px[c] << (8 * (b & 3)));
+                    }
                 }
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        bf16x8v *dst = reinterpret_cast<bf16x8v *>(x0 + (2 * lane + k + kCnnGuard) * 24);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            bf16x8v o;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                o[e] = to_bf16(((float)v[k][8 * c + e] - 128.0f) * (1.0f / 64.0f));
-            dst[c] = o;
-        }
-    }
+    store_row24(x0 + (2 * lane + kCnnGuard) * 24, u[0]);
+    store_row24(x0 + (2 * lane + 1 + kCnnGuard) * 24, u[1]);
 }
 
 // --------------------------------------------------------------- kernels --
@@ -466,7 +489,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_windows(const uint8_t *mo
 // by the network, best pixel of each half (ties: outermost).  A workgroup of
 // kCnnWaveBlock / 64 waves takes items in turn (XCD-aware slices); its waves
 // share an item's windows.
-__global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_strips(CnnStripArgs a)
+__global__ __launch_bounds__(kCnnWaveBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_cnn_strips(CnnStripArgs a)
 {
     extern __shared__ __align__(16) uint8_t cnn_smem[];
     __shared__ uint64_t s_best[kCnnWaveBlock / 64][2];
