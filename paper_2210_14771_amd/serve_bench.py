@@ -45,6 +45,10 @@ OPEN_ISSUE = ("serve_bench is switched off: its realtime run (after a warm-up se
 
 def main():
     raise SystemExit(OPEN_ISSUE)
+
+
+def run_benchmark():
+    """The benchmark proper (not run while OPEN_ISSUE stands)."""
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--streams", type=int, default=48)
     # a server has so far only been run to about 900 batches (0.4 s of the
