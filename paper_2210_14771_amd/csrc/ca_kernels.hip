@@ -198,76 +198,36 @@ __device__ void load_hstrip(const uint8_t *frame, int W, int rs, int row, uint8_
 }
 
 // Stage luma of the three columns of a vertical strip centred on `col`.
-// Rows 1 .. H-2 always hold the 9 bytes inside 3 aligned dwords that lie in
-// the frame (1 <= col <= W-2 and the row stride is at least 3W >= 48), so
-// their loads need no check; each thread keeps 4 rows of loads in flight
-// (addresses clamped to the last such row, stores masked).  Rows 0 and H-1
-// take the checked path.
-__device__ __forceinline__ void vstrip_row(const uint8_t *frame, const uintptr_t fstart,
-                                           const uintptr_t fend, int y, int rs, int col,
-                                           uint8_t *tile, int LP)
-{
-    const uint8_t *p = frame + (int64_t)y * rs + 3 * (col - 1);
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
-    const uint32_t sh = (uint32_t)(addr & 3);
-    const uintptr_t al = addr - sh;
-    uint32_t b03, b47, b8;
-    if (al >= fstart && al + 12 <= fend) {
-        const uint32_t *w = reinterpret_cast<const uint32_t *>(p - sh);
-        const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
-        b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
-        b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
-        b8 = (w2 >> (8 * sh)) & 0xFFu;
-    } else {
-        b03 = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16)
-              | ((uint32_t)p[3] << 24);
-        b47 = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16)
-              | ((uint32_t)p[7] << 24);
-        b8 = p[8];
-    }
-    tile[0 * LP + y] = (uint8_t)luma_of(b03 & 0xFFu, (b03 >> 8) & 0xFFu, (b03 >> 16) & 0xFFu);
-    tile[1 * LP + y] = (uint8_t)luma_of(b03 >> 24, b47 & 0xFFu, (b47 >> 8) & 0xFFu);
-    tile[2 * LP + y] = (uint8_t)luma_of((b47 >> 16) & 0xFFu, b47 >> 24, b8);
-}
-
 __device__ void load_vstrip(const uint8_t *frame, int W, int H, int rs, int col, uint8_t *tile,
                             int LP)
 {
-    constexpr int R = 4;
     const uintptr_t fstart = reinterpret_cast<uintptr_t>(frame);
     const uintptr_t fend = fstart + (uintptr_t)((int64_t)(H - 1) * rs + 3 * W);
-    const uint8_t *base = frame + 3 * (col - 1);
-    for (int y0 = 1 + (int)threadIdx.x; y0 < H - 1; y0 += kBlock * R) {
-        uint32_t w[R][3], sh[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            int y = y0 + r * kBlock;
-            y = y < H - 2 ? y : H - 2;
-            const uint8_t *p = base + (int64_t)y * rs;
-            sh[r] = (uint32_t)(reinterpret_cast<uintptr_t>(p) & 3);
-            const uint32_t *q = reinterpret_cast<const uint32_t *>(p - sh[r]);
-            w[r][0] = q[0];
-            w[r][1] = q[1];
-            w[r][2] = q[2];
+    for (int y = threadIdx.x; y < H; y += kBlock) {
+        const uint8_t *p = frame + (int64_t)y * rs + 3 * (col - 1);
+        const uintptr_t addr = reinterpret_cast<uintptr_t>(p);
+        const uint32_t sh = (uint32_t)(addr & 3);
+        const uintptr_t al = addr - sh;
+        uint32_t b03, b47, b8;
+        if (al >= fstart && al + 12 <= fend) {
+            // the 9 bytes lie inside 3 aligned dwords; extract with v_alignbyte.
+            // (pointer arithmetic, not integer casts, keeps the global address space)
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(p - sh);
+            const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+            b03 = __builtin_amdgcn_alignbyte(w1, w0, sh);
+            b47 = __builtin_amdgcn_alignbyte(w2, w1, sh);
+            b8 = (w2 >> (8 * sh)) & 0xFFu;
+        } else {
+            b03 = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16)
+                  | ((uint32_t)p[3] << 24);
+            b47 = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16)
+                  | ((uint32_t)p[7] << 24);
+            b8 = p[8];
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int y = y0 + r * kBlock;
-            if (y < H - 1) {
-                const uint32_t b03 = __builtin_amdgcn_alignbyte(w[r][1], w[r][0], sh[r]);
-                const uint32_t b47 = __builtin_amdgcn_alignbyte(w[r][2], w[r][1], sh[r]);
-                const uint32_t b8 = (w[r][2] >> (8 * sh[r])) & 0xFFu;
-                tile[0 * LP + y] =
-                    (uint8_t)luma_of(b03 & 0xFFu, (b03 >> 8) & 0xFFu, (b03 >> 16) & 0xFFu);
-                tile[1 * LP + y] = (uint8_t)luma_of(b03 >> 24, b47 & 0xFFu, (b47 >> 8) & 0xFFu);
-                tile[2 * LP + y] = (uint8_t)luma_of((b47 >> 16) & 0xFFu, b47 >> 24, b8);
-            }
-        }
+        tile[0 * LP + y] = (uint8_t)luma_of(b03 & 0xFFu, (b03 >> 8) & 0xFFu, (b03 >> 16) & 0xFFu);
+        tile[1 * LP + y] = (uint8_t)luma_of(b03 >> 24, b47 & 0xFFu, (b47 >> 8) & 0xFFu);
+        tile[2 * LP + y] = (uint8_t)luma_of((b47 >> 16) & 0xFFu, b47 >> 24, b8);
     }
-    if (threadIdx.x == 0)
-        vstrip_row(frame, fstart, fend, 0, rs, col, tile, LP);
-    if (threadIdx.x == 1 && H > 1)
-        vstrip_row(frame, fstart, fend, H - 1, rs, col, tile, LP);
 }
 
 struct StripLds {
