@@ -239,6 +239,17 @@ def mixed_section(args, est, kw):
             "frame_bytes": int(sum(sizes))}
 
 
+def run_environment(params) -> dict:
+    import torch
+    try:
+        rocm = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        rocm = None
+    return {"rocm": rocm, "torch": torch.__version__, "hip": torch.version.hip,
+            "device": torch.cuda.get_device_name(0), "host_cpus": os.cpu_count(),
+            "seed": int(params.seed), "data_seed": "SeedSequence([2210_14771, config, frame])"}
+
+
 def cpu_baseline(frames, kw, target_cpu_s: float):
     import oracle
     threads = max(1, min(os.cpu_count() or 1, 16))
@@ -441,6 +452,7 @@ def main():
     mixed = mixed_section(args, est, kw)
     if mixed is not None:
         line["mixed_512"] = mixed
+    line["env"] = run_environment(params)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(frames, kw, args.cpu_seconds)
