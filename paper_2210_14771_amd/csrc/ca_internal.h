@@ -11,7 +11,7 @@ namespace ca {
 
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kHalfThreads = 128; // threads per half strip
-constexpr int kLanesPerAttempt = 4;                        // lanes sharing one RANSAC attempt
+constexpr int kLanesPerAttempt = 2;                        // lanes sharing one RANSAC attempt
 constexpr int kAttemptsPerGroup = kBlock / kLanesPerAttempt; // attempts per RANSAC workgroup
 constexpr int kChunk = 16;       // most pixels one thread scores per pass
 constexpr int kQtBins = 2049;    // pseudo-angle bins, 0 .. 2048

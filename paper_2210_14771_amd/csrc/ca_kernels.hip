@@ -344,12 +344,14 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
 
 // ------------------------------------------------------------ RANSAC ------
 
+// Kept points of one frame in LDS, compacted in canonical order and padded
+// to a multiple of the lanes per attempt with far-away points whose moments
+// are zero (never inside a band, so they add nothing).
 struct Lds {
     double2 uv[kBlock];     // shifted coordinates u, v
     double2 m1[kBlock];     // u^2, u v
-    double2 m2[kBlock];     // v^2, z = u^2 + v^2
-    double2 m3[kBlock];     // u z, v z
-    double q[kBlock];       // floor(score * 2^24)
+    double2 m2[kBlock];     // v^2, floor(score * 2^24)
+    double2 m3[kBlock];     // u z, v z  (z = u^2 + v^2)
     int iu[kBlock], iv[kBlock];
     int wcount[4];
     uint64_t wbest[4];
@@ -443,7 +445,7 @@ __device__ __forceinline__ Band make_band(double cx, double cy, double r2, doubl
     return b;
 }
 
-// Sum over the 4 lanes of a quad (the lanes of one attempt).  The partial
+// Sum over the lanes of one attempt (adjacent lanes of a quad).  The partial
 // sums are integers below 2^53, so every order gives the same exact total.
 template <int kCtrl>
 __device__ __forceinline__ double quad_xor(double v)
@@ -452,73 +454,177 @@ __device__ __forceinline__ double quad_xor(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double quad_sum(double v)
+__device__ __forceinline__ double lane_sum(double v)
 {
-    static_assert(kLanesPerAttempt == 4, "quad reduction");
-    v += quad_xor<0xB1>(v);  // quad_perm [1, 0, 3, 2]
-    v += quad_xor<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    static_assert(kLanesPerAttempt == 1 || kLanesPerAttempt == 2 || kLanesPerAttempt == 4,
+                  "attempt lanes");
+    if (kLanesPerAttempt >= 2)
+        v += quad_xor<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    if (kLanesPerAttempt >= 4)
+        v += quad_xor<0x4E>(v);  // quad_perm [2, 3, 0, 1]
     return v;
 }
 
-// One inlier pass + Coope least-squares refit (Section 2.2.5).  Lane `sub`
-// of the attempt's quad takes points sub, sub + 4, ...
-__device__ bool refit(const Lds &L, int n, int sub, const Band &b, double &cx, double &cy,
-                      double &r2)
+__device__ __forceinline__ double in_band(const double2 p, const Band &b)
 {
-    double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0, S5 = 0, S6 = 0, S7 = 0, S8 = 0;
-    for (int i = sub; i < n; i += kLanesPerAttempt) {
+    const double du = p.x - b.cx;
+    const double dv = p.y - b.cy;
+    const double d2 = du * du + dv * dv;
+    return (b.lo2 <= d2 && d2 <= b.hi2) ? 1.0 : 0.0;
+}
+
+// Inlier moments of one band: count, sum u, v, u^2, u v, v^2, u z, v z.
+struct Moments {
+    double m, su, sv, suu, suv, svv, suz, svz;
+};
+
+// Lane `sub` of the attempt takes points sub, sub + kLanesPerAttempt, ...;
+// nk = padded point count / kLanesPerAttempt (wave-uniform).
+__device__ Moments band_moments(const Lds &L, int nk, int sub, const Band &b)
+{
+    Moments s = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < nk; ++k) {
+        const int i = k * kLanesPerAttempt + sub;
         const double2 p = L.uv[i];
-        const double du = p.x - b.cx;
-        const double dv = p.y - b.cy;
-        const double d2 = du * du + dv * dv;
-        const double w = (b.lo2 <= d2 && d2 <= b.hi2) ? 1.0 : 0.0;
+        const double w = in_band(p, b);
         const double2 m1 = L.m1[i], m2 = L.m2[i], m3 = L.m3[i];
-        S0 += w;
-        S1 = fma(w, p.x, S1);
-        S2 = fma(w, p.y, S2);
-        S3 = fma(w, m1.x, S3);
-        S4 = fma(w, m1.y, S4);
-        S5 = fma(w, m2.x, S5);
-        S6 = fma(w, m2.y, S6);
-        S7 = fma(w, m3.x, S7);
-        S8 = fma(w, m3.y, S8);
+        s.m += w;
+        s.su = fma(w, p.x, s.su);
+        s.sv = fma(w, p.y, s.sv);
+        s.suu = fma(w, m1.x, s.suu);
+        s.suv = fma(w, m1.y, s.suv);
+        s.svv = fma(w, m2.x, s.svv);
+        s.suz = fma(w, m3.x, s.suz);
+        s.svz = fma(w, m3.y, s.svz);
     }
-    S0 = quad_sum(S0);
-    S1 = quad_sum(S1);
-    S2 = quad_sum(S2);
-    S3 = quad_sum(S3);
-    S4 = quad_sum(S4);
-    S5 = quad_sum(S5);
-    S6 = quad_sum(S6);
-    S7 = quad_sum(S7);
-    S8 = quad_sum(S8);
-    const int64_t m = (int64_t)S0;
-    if (m < 3)
+    s.m = lane_sum(s.m);
+    s.su = lane_sum(s.su);
+    s.sv = lane_sum(s.sv);
+    s.suu = lane_sum(s.suu);
+    s.suv = lane_sum(s.suv);
+    s.svv = lane_sum(s.svv);
+    s.suz = lane_sum(s.suz);
+    s.svz = lane_sum(s.svz);
+    return s;
+}
+
+// Coope least-squares circle from the inlier moments (Section 2.2.5).  The
+// centred sums C = m S_ab - S_a S_b are integers; with kExact (every product
+// below 2^53 for this frame's coordinate range and point count) they are
+// formed in float64, where each product and difference is exact, otherwise in
+// int64.  Both give the same doubles.  The sum of z is S_uu + S_vv.
+template <bool kExact>
+__device__ bool coope_solve(const Moments &s, double &cx, double &cy, double &r2)
+{
+    if (s.m < 3.0)
         return false;
-    const int64_t Su = (int64_t)S1, Sv = (int64_t)S2, Suu = (int64_t)S3, Suv = (int64_t)S4;
-    const int64_t Svv = (int64_t)S5, Sz = (int64_t)S6, Suz = (int64_t)S7, Svz = (int64_t)S8;
-    const int64_t Cuu = m * Suu - Su * Su;
-    const int64_t Cuv = m * Suv - Su * Sv;
-    const int64_t Cvv = m * Svv - Sv * Sv;
-    const int64_t Cuz = m * Suz - Su * Sz;
-    const int64_t Cvz = m * Svz - Sv * Sz;
-    const double det = (double)Cuu * (double)Cvv - (double)Cuv * (double)Cuv;
+    const double m = s.m;
+    const double sz = s.suu + s.svv;
+    double Cuu, Cuv, Cvv, Cuz, Cvz;
+    if (kExact) {
+        Cuu = m * s.suu - s.su * s.su;
+        Cuv = m * s.suv - s.su * s.sv;
+        Cvv = m * s.svv - s.sv * s.sv;
+        Cuz = m * s.suz - s.su * sz;
+        Cvz = m * s.svz - s.sv * sz;
+    } else {
+        const int64_t im = (int64_t)s.m, su = (int64_t)s.su, sv = (int64_t)s.sv;
+        const int64_t suu = (int64_t)s.suu, svv = (int64_t)s.svv, isz = suu + svv;
+        Cuu = (double)(im * suu - su * su);
+        Cuv = (double)(im * (int64_t)s.suv - su * sv);
+        Cvv = (double)(im * svv - sv * sv);
+        Cuz = (double)(im * (int64_t)s.suz - su * isz);
+        Cvz = (double)(im * (int64_t)s.svz - sv * isz);
+    }
+    const double det = Cuu * Cvv - Cuv * Cuv;
     if (det == 0.0)
         return false;
-    const double A = ((double)Cuz * (double)Cvv - (double)Cvz * (double)Cuv) / det;
-    const double B = ((double)Cvz * (double)Cuu - (double)Cuz * (double)Cuv) / det;
+    const double A = (Cuz * Cvv - Cvz * Cuv) / det;
+    const double B = (Cvz * Cuu - Cuz * Cuv) / det;
     cx = A / 2.0;
     cy = B / 2.0;
-    const double mu = (double)Su / (double)m;
-    const double mv = (double)Sv / (double)m;
-    const double var = (double)(Cuu + Cvv) / ((double)m * (double)m);
+    const double mu = s.su / m;
+    const double mv = s.sv / m;
+    const double var = (Cuu + Cvv) / (m * m);
     r2 = (var + (mu - cx) * (mu - cx)) + (mv - cy) * (mv - cy);
     return true;
 }
 
-// One RANSAC item: attempts [g * 64, g * 64 + 64) of frame f, four lanes per
-// attempt.  Writes the group's best attempt to its record (device scope) and
-// ends with a barrier.
+// One attempt (Section 2.2.5): draw a triple, circle through it, `refine`
+// inlier passes with least-squares refits, then count the inliers and their
+// score sum and apply the circle limits.  `key` is set for kept circles (on
+// the attempt's first lane).
+template <bool kExact>
+__device__ void run_attempt(const RansacArgs &a, const Lds &L, const FrameDev &d, int n, int nk,
+                            int sub, int att, bool active, ca_attempt &rec, uint64_t &key)
+{
+    const int ox = d.W / 2, oy = d.H / 2;
+    if (n >= 3 && active) {
+        int t[3];
+        if (!pick_triple(a, d.uid, att, n, t)) {
+            rec.i0 = rec.i1 = rec.i2 = -1;
+            rec.fail_stage = -1;
+        } else {
+            rec.i0 = t[0];
+            rec.i1 = t[1];
+            rec.i2 = t[2];
+            const int64_t x0 = L.iu[t[0]], x1 = L.iu[t[1]], x2 = L.iu[t[2]];
+            const int64_t y0 = L.iv[t[0]], y1 = L.iv[t[1]], y2 = L.iv[t[2]];
+            const int64_t D = 2 * (x0 * (y1 - y2) + x1 * (y2 - y0) + x2 * (y0 - y1));
+            bool ok = D != 0;
+            double cx = 0, cy = 0, r2 = 0;
+            if (ok) {
+                const int64_t z0 = x0 * x0 + y0 * y0, z1 = x1 * x1 + y1 * y1, z2 = x2 * x2 + y2 * y2;
+                const int64_t Nx = z0 * (y1 - y2) + z1 * (y2 - y0) + z2 * (y0 - y1);
+                const int64_t Ny = z0 * (x2 - x1) + z1 * (x0 - x2) + z2 * (x1 - x0);
+                cx = (double)Nx / (double)D;
+                cy = (double)Ny / (double)D;
+                const double ddx = (double)x0 - cx, ddy = (double)y0 - cy;
+                r2 = ddx * ddx + ddy * ddy;
+                for (int k = 1; k <= a.refine; ++k) {
+                    const Band bd = make_band(cx, cy, r2, a.t_ri);
+                    if (!coope_solve<kExact>(band_moments(L, nk, sub, bd), cx, cy, r2)) {
+                        rec.fail_stage = k;
+                        ok = false;
+                        break;
+                    }
+                }
+            }
+            if (ok) {
+                const Band bd = make_band(cx, cy, r2, a.t_ri);
+                double cnt = 0, qs = 0;
+                for (int k = 0; k < nk; ++k) {
+                    const int i = k * kLanesPerAttempt + sub;
+                    const double w = in_band(L.uv[i], bd);
+                    cnt += w;
+                    qs = fma(w, L.m2[i].y, qs);
+                }
+                cnt = lane_sum(cnt);
+                qs = lane_sum(qs);
+                const double acx = (double)ox + cx;
+                const double acy = (double)oy + cy;
+                const double r = sqrt(r2);
+                const double ex = acx - (double)(d.W - 1) / 2.0;
+                const double ey = acy - (double)(d.H - 1) / 2.0;
+                const double dlim = a.d_max * (double)d.W;
+                const bool kept = r >= a.r_min * (double)d.W && r <= a.r_max * (double)d.W
+                                  && ex * ex + ey * ey <= dlim * dlim;
+                rec.status = kept ? 2 : 1;
+                rec.inliers = (int32_t)cnt;
+                rec.qsum = (uint64_t)qs;
+                rec.cx = acx;
+                rec.cy = acy;
+                rec.r2 = r2;
+                if (kept && sub == 0)
+                    key = (rec.qsum << 16) | (uint64_t)(0xFFFFu - (uint32_t)att);
+            }
+        }
+    }
+}
+
+// One RANSAC item: attempts [g * A, g * A + A) of frame f (A =
+// kAttemptsPerGroup), kLanesPerAttempt lanes per attempt.  Writes the group's
+// best attempt to its record (device scope) and ends with a barrier.
 __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
 {
     const int tid = threadIdx.x;
@@ -551,7 +657,8 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
     int base = 0;
     for (int w = 0; w < wv; ++w)
         base += L.wcount[w];
-    const int n = L.wcount[0] + L.wcount[1] + L.wcount[2] + L.wcount[3];
+    const int n = uniform(L.wcount[0] + L.wcount[1] + L.wcount[2] + L.wcount[3]);
+    const int nk = (n + kLanesPerAttempt - 1) / kLanesPerAttempt;
     if (keep) {
         const int j = base + before;
         const int u = x - ox, v = y - oy;
@@ -561,81 +668,33 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
         L.iv[j] = v;
         L.uv[j] = make_double2(du, dv);
         L.m1[j] = make_double2((double)((int64_t)u * u), (double)((int64_t)u * v));
-        L.m2[j] = make_double2((double)((int64_t)v * v), z);
+        L.m2[j] = make_double2((double)((int64_t)v * v), (double)(uint32_t)(sc * 16777216.0f));
         L.m3[j] = make_double2(du * z, dv * z);
-        L.q[j] = (double)(uint32_t)(sc * 16777216.0f);
+    }
+    if (tid >= n && tid < nk * kLanesPerAttempt) {
+        // padding: squared distance ~1e300 exceeds every band's outer radius
+        L.uv[tid] = make_double2(1e150, 1e150);
+        L.m1[tid] = make_double2(0.0, 0.0);
+        L.m2[tid] = make_double2(0.0, 0.0);
+        L.m3[tid] = make_double2(0.0, 0.0);
     }
     __syncthreads();
+
+    // every centred product below 2^53: float64 arithmetic is exact
+    const double U = (double)(ox > d.W - 1 - ox ? ox : d.W - 1 - ox);
+    const double V = (double)(oy > d.H - 1 - oy ? oy : d.H - 1 - oy);
+    const bool exact =
+        uniform((double)n * (double)n * (U > V ? U : V) * (U * U + V * V) < 0x1p52 ? 1 : 0) != 0;
 
     const int sub = tid & (kLanesPerAttempt - 1);
     const int att = g * kAttemptsPerGroup + tid / kLanesPerAttempt;
     const bool active = att < a.attempts;
     uint64_t key = 0;
     ca_attempt rec = {};
-    if (n >= 3 && active) {
-        int t[3];
-        if (!pick_triple(a, d.uid, att, n, t)) {
-            rec.i0 = rec.i1 = rec.i2 = -1;
-            rec.fail_stage = -1;
-        } else {
-            rec.i0 = t[0];
-            rec.i1 = t[1];
-            rec.i2 = t[2];
-            const int64_t x0 = L.iu[t[0]], x1 = L.iu[t[1]], x2 = L.iu[t[2]];
-            const int64_t y0 = L.iv[t[0]], y1 = L.iv[t[1]], y2 = L.iv[t[2]];
-            const int64_t D = 2 * (x0 * (y1 - y2) + x1 * (y2 - y0) + x2 * (y0 - y1));
-            bool ok = D != 0;
-            double cx = 0, cy = 0, r2 = 0;
-            if (ok) {
-                const int64_t z0 = x0 * x0 + y0 * y0, z1 = x1 * x1 + y1 * y1, z2 = x2 * x2 + y2 * y2;
-                const int64_t Nx = z0 * (y1 - y2) + z1 * (y2 - y0) + z2 * (y0 - y1);
-                const int64_t Ny = z0 * (x2 - x1) + z1 * (x0 - x2) + z2 * (x1 - x0);
-                cx = (double)Nx / (double)D;
-                cy = (double)Ny / (double)D;
-                const double ddx = (double)x0 - cx, ddy = (double)y0 - cy;
-                r2 = ddx * ddx + ddy * ddy;
-                for (int k = 1; k <= a.refine; ++k) {
-                    const Band bd = make_band(cx, cy, r2, a.t_ri);
-                    if (!refit(L, n, sub, bd, cx, cy, r2)) {
-                        rec.fail_stage = k;
-                        ok = false;
-                        break;
-                    }
-                }
-            }
-            if (ok) {
-                const Band bd = make_band(cx, cy, r2, a.t_ri);
-                double cnt = 0, qs = 0;
-                for (int i = sub; i < n; i += kLanesPerAttempt) {
-                    const double2 p = L.uv[i];
-                    const double du = p.x - bd.cx;
-                    const double dv = p.y - bd.cy;
-                    const double d2 = du * du + dv * dv;
-                    const double w = (bd.lo2 <= d2 && d2 <= bd.hi2) ? 1.0 : 0.0;
-                    cnt += w;
-                    qs = fma(w, L.q[i], qs);
-                }
-                cnt = quad_sum(cnt);
-                qs = quad_sum(qs);
-                const double acx = (double)ox + cx;
-                const double acy = (double)oy + cy;
-                const double r = sqrt(r2);
-                const double ex = acx - (double)(d.W - 1) / 2.0;
-                const double ey = acy - (double)(d.H - 1) / 2.0;
-                const double dlim = a.d_max * (double)d.W;
-                const bool kept = r >= a.r_min * (double)d.W && r <= a.r_max * (double)d.W
-                                  && ex * ex + ey * ey <= dlim * dlim;
-                rec.status = kept ? 2 : 1;
-                rec.inliers = (int32_t)cnt;
-                rec.qsum = (uint64_t)qs;
-                rec.cx = acx;
-                rec.cy = acy;
-                rec.r2 = r2;
-                if (kept && sub == 0)
-                    key = (rec.qsum << 16) | (uint64_t)(0xFFFFu - (uint32_t)att);
-            }
-        }
-    }
+    if (exact)
+        run_attempt<true>(a, L, d, n, nk, sub, att, active, rec, key);
+    else
+        run_attempt<false>(a, L, d, n, nk, sub, att, active, rec, key);
     if (a.dbg && active && sub == 0)
         a.dbg[(int64_t)f * a.attempts + att] = rec;
 

@@ -81,6 +81,21 @@ def test_hd_workload_parity(torch_dev, est, hd_batch):
     assert bits[0] == bits[1]
 
 
+@pytest.fixture(scope="module")
+def wide_batch():
+    return np.stack([synth.make_frame(synth.HD_1080p, 300 + i, 8192, 2048)[0] for i in range(2)])
+
+
+def test_large_extent_parity(torch_dev, est, wide_batch):
+    # 8192 x 2048 frames: once 8 or more points are kept, the centred moment
+    # products of the refit reach 2^52, so they are formed in int64 rather
+    # than float64; both forms must agree with the oracle bit for bit
+    g, r, bits = _full_parity(torch_dev, est, wide_batch, dict(HD, ransac_attempts=256),
+                              uids=[300, 301])
+    assert min(int(x["n_points"]) for x in r) >= 8
+    assert bits[0] == bits[1]
+
+
 def test_enumeration_equals_brute_force(torch_dev, est):
     # tiny frames: every triple of the kept points is tried once
     frames, _ = synth.make_batch(synth.SMALL_640x480, 6)
