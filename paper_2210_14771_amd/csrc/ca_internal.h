@@ -13,7 +13,7 @@ constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kHalfThreads = 128; // threads per half strip
 constexpr int kLanesPerAttempt = 2;                        // lanes sharing one RANSAC attempt
 constexpr int kAttemptsPerGroup = kBlock / kLanesPerAttempt; // attempts per RANSAC workgroup
-constexpr int kChunk = 16;       // most pixels one thread scores per pass
+constexpr int kChunk = 8;        // most pixels one thread scores per pass (a 1920-pixel line in one pass)
 constexpr int kQtBins = 2049;    // pseudo-angle bins, 0 .. 2048
 constexpr int kLumaLevels = 256;
 
