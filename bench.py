@@ -2,7 +2,11 @@
 
 One step = one call of the whole hot path (strip scoring, candidate
 selection, RANSAC with refits, best-circle selection) on a batch of 64
-synthetic 1920x1080 RGB frames already resident in HBM.  Prints one JSON
+synthetic 1920x1080 RGB frames already resident in HBM.  The timed steps
+replay captured HIP graphs with two batches in flight (two contexts on two
+HIP streams taking turns, so one batch's FP64 RANSAC overlaps the next
+batch's strip loads); the same steps with one batch in flight, and eager
+calls, are reported beside.  Prints one JSON
 line with frames/s, per-call latency percentiles, the dominant kernel's
 roofline position (kernel time from HIP events recorded inside the library
 on the launch stream), accuracy against the synthetic ground truth, and the
@@ -42,6 +46,9 @@ def parse():
                          "the batch")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="batches in flight in the timed region: contexts, each with its own "
+                         "plan buffers, output and HIP stream, taking the graphs in turn")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
     ap.add_argument("--lag", type=int, default=None)
     ap.add_argument("--queues", type=int, default=None)
@@ -299,23 +306,29 @@ def main():
         # further resident batches: mirrored copies (different bytes, same work)
         resident.append(resident[0].flip(2 if k % 2 else 1).contiguous())
     uids = list(range(B))
-    est = api.Estimator(0)
-    est.set_option("schedule", args.schedule)
-    if args.lag is not None:
-        est.set_option("lag", args.lag)
-    if args.queues is not None:
-        est.set_option("queues", args.queues)
-    if args.pipeline is not None:
-        est.set_option("pipeline", args.pipeline)
-    pipeline = est.get_option("pipeline")
     params = api.default_params(**kw)
+
+    def make_estimator():
+        e = api.Estimator(0)
+        e.set_option("schedule", args.schedule)
+        if args.lag is not None:
+            e.set_option("lag", args.lag)
+        if args.queues is not None:
+            e.set_option("queues", args.queues)
+        if args.pipeline is not None:
+            e.set_option("pipeline", args.pipeline)
+        tiles = {}
+        if args.schedule == "auto":
+            for r in resident:
+                tiles = e.autotune(r, params, uids, reps=20)
+        return e, tiles
+
+    print("# autotune", file=sys.stderr, flush=True)
+    est, tiles = make_estimator()
+    pipeline = est.get_option("pipeline")
     out = torch.empty((B, 8), dtype=torch.int32, device=dev)
     tuning = None
     if args.schedule == "auto":
-        print("# autotune", file=sys.stderr, flush=True)
-        tiles = {}
-        for r in resident:
-            tiles = est.autotune(r, params, uids, reps=20)
         schedule_used = est.last_tuned_schedule or "split"
         tuning = {"schedule": schedule_used,
                   "strips_per_group": {f"{w}x{h}": t for (w, h), t in tiles.items()}}
@@ -347,21 +360,47 @@ def main():
     elapsed_eager = time.perf_counter() - t0
     print("# eager region done", file=sys.stderr, flush=True)
 
-    # timed region: the same K calls replayed from captured HIP graphs
-    # (G calls per graph, one graph per resident batch, alternating)
+    # timed region: the same K calls replayed from captured HIP graphs (G
+    # calls per graph, one graph per resident batch per context).  With
+    # several batches in flight, each context (its own plan buffers, output
+    # and HIP stream) takes the graphs in turn, so one batch's RANSAC (FP64
+    # ALU) overlaps the next one's strip loads (HBM); every batch still runs
+    # the whole path.
     G = args.graph_calls if K % args.graph_calls == 0 else 1
-    graphs = [est.capture(r, params, uids, out=out, calls=G) for r in resident]
-    for g in graphs:
-        g.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K // G):
-        graphs[i % len(graphs)].launch()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for g in graphs:
-        g.close()
-    est.device_status()
+    n_inflight = max(1, args.inflight)
+    extra = [make_estimator()[0] for _ in range(n_inflight - 1)]
+    ests = [est] + extra
+    outs = [out] + [torch.empty_like(out) for _ in extra]
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in extra]
+
+    def graph_region(n):
+        graphs = [[ests[k].capture(r, params, uids, out=outs[k], calls=G) for r in resident]
+                  for k in range(n)]
+        for k in range(n):
+            for g in graphs[k]:
+                g.launch(streams[k])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(K // G):
+            k = i % n
+            graphs[k][(i // n) % len(resident)].launch(streams[k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for gs in graphs:
+            for g in gs:
+                g.close()
+        return dt
+
+    elapsed_one = graph_region(1)
+    elapsed = graph_region(n_inflight) if n_inflight > 1 else elapsed_one
+    for e in ests:
+        e.device_status()
+    # every context gives the same results
+    ref = est.estimate_area(resident[0], params, uids).raw
+    inflight_identical = all(
+        torch.equal(e.estimate_area(resident[0], params, uids).raw, ref) for e in extra)
+    for e in extra:
+        e.close()
     print("# graph region done", file=sys.stderr, flush=True)
 
     # per-call latency: each call waited for on its own
@@ -433,7 +472,12 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency_note": "per call of 64 frames, each call synchronised on its own",
-        "timing": f"K steps replayed from HIP graphs of {G} calls; eager calls below",
+        "timing": f"K steps replayed from HIP graphs of {G} calls, {n_inflight} batches in "
+                  f"flight ({n_inflight} contexts and HIP streams taking the graphs in turn); "
+                  f"one batch in flight and eager calls below",
+        "inflight": {"batches": n_inflight, "results_identical": bool(inflight_identical)},
+        "one_in_flight_value": B * K / elapsed_one,
+        "one_in_flight_ms_per_step": elapsed_one / K * 1e3,
         "eager_value": B * K / elapsed_eager,
         "eager_ms_per_step": elapsed_eager / K * 1e3,
         "schedule": schedule_used,
