@@ -140,7 +140,13 @@ __device__ void zero_guards(__bf16 *buf, int chans)
 // layer is folded into the last convolution's epilogue (a sum over the four
 // lane groups holding a position's 16 channels).
 
-constexpr int kWaveBytes = kCnnRows * (24 + 32 + 32) * 2;   // x0, ha, hb of one wave
+// Two activation buffers per wave, 32 channels wide, used in turn: A holds
+// the input (24 channels) and later the second layer's output, B the first
+// and the third layer's.  Rows of one layout read under another (guard rows,
+// the tail of a narrower layout) hold stale finite values; they only ever
+// feed halo positions, whose outputs are discarded.
+constexpr int kWaveBuf = kCnnRows * 32;                   // bf16 elements per buffer
+constexpr int kWaveBytes = 2 * kWaveBuf * 2;              // A and B of one wave
 
 struct WaveFrag {
     bf16x8 w1[1][4];
@@ -207,12 +213,13 @@ __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float
     for (int g = 0; g < kCnnWin / 16 / kNB; ++g) {
         const int n0 = g * kNB * 16 + (lane & 15);
         const __bf16 *b0 = X + (n0 + kCnnGuard - 2) * CIN + kq;
+        // accumulators start at the bias
         f32x4 acc[kNB][MT];
 #pragma unroll
         for (int t = 0; t < kNB; ++t)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                acc[t][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                acc[t][mt] = f32x4{bias[mt][0], bias[mt][1], bias[mt][2], bias[mt][3]};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             bf16x8 bv[kNB];
@@ -229,16 +236,15 @@ __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float
 #pragma unroll
         for (int t = 0; t < kNB; ++t) {
             const int n = n0 + 16 * t;
-            const bool inside = n >= lo && n < hi;
+            // ReLU and the strip mask in one median: clamp to [0, +inf)
+            // inside the strip, to [0, 0] outside
+            const float top = (n >= lo && n < hi) ? __builtin_inff() : 0.0f;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 bf16x4 o;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float v = acc[t][mt][j] + bias[mt][j];
-                    v = v > 0.0f ? v : 0.0f;
-                    o[j] = to_bf16(inside ? v : 0.0f);
-                }
+                for (int j = 0; j < 4; ++j)
+                    o[j] = to_bf16(__builtin_amdgcn_fmed3f(acc[t][mt][j], 0.0f, top));
                 *reinterpret_cast<bf16x4 *>(Y + (n + kCnnGuard) * COUT + mt * 16 + 4 * (lane >> 4)) =
                     o;
             }
@@ -261,7 +267,7 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
         f32x4 acc[kNB];
 #pragma unroll
         for (int t = 0; t < kNB; ++t)
-            acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            acc[t] = f32x4{fr.b4[0][0], fr.b4[0][1], fr.b4[0][2], fr.b4[0][3]};
 #pragma unroll
         for (int ks = 0; ks < 5; ++ks) {
             bf16x8 bv[kNB];
@@ -276,13 +282,11 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
 #pragma unroll
         for (int t = 0; t < kNB; ++t) {
             const int n = n0 + 16 * t;
-            const bool inside = n >= lo && n < hi;
+            const float top = (n >= lo && n < hi) ? __builtin_inff() : 0.0f;
             float part = 0.0f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float v = acc[t][j] + fr.b4[0][j];
-                v = v > 0.0f ? v : 0.0f;
-                const float h = inside ? (float)to_bf16(v) : 0.0f;
+                const float h = (float)to_bf16(__builtin_amdgcn_fmed3f(acc[t][j], 0.0f, top));
                 part = fmaf(fr.w5[j], h, part);
             }
             part += __shfl_xor(part, 16, 64);
@@ -296,17 +300,17 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
 // Logits of one window whose input rows are in w.x0: all 128 positions, in
 // 8 calls of emit (positions outside the strip carry unspecified values).
 template <typename Emit>
-__device__ __forceinline__ void wave_forward(const WaveFrag &fr, __bf16 *x0, __bf16 *ha, __bf16 *hb,
-                                             int lo, int hi, int lane, Emit emit)
+__device__ __forceinline__ void wave_forward(const WaveFrag &fr, __bf16 *A, __bf16 *B, int lo,
+                                             int hi, int lane, Emit emit)
 {
     wave_sync();
-    wave_conv<24, 16, 1, 4>(fr.w1, fr.b1, x0, ha, lo, hi, lane);
+    wave_conv<24, 16, 1, 4>(fr.w1, fr.b1, A, B, lo, hi, lane);
     wave_sync();
-    wave_conv<16, 32, 2, 3>(fr.w2, fr.b2, ha, hb, lo, hi, lane);
+    wave_conv<16, 32, 2, 3>(fr.w2, fr.b2, B, A, lo, hi, lane);
     wave_sync();
-    wave_conv<32, 32, 2, 5>(fr.w3, fr.b3, hb, ha, lo, hi, lane);
+    wave_conv<32, 32, 2, 5>(fr.w3, fr.b3, A, B, lo, hi, lane);
     wave_sync();
-    wave_conv_out(fr, ha, lo, hi, lane, emit);
+    wave_conv_out(fr, B, lo, hi, lane, emit);
     wave_sync();
 }
 
@@ -460,8 +464,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_windows(const uint8_t *mo
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     __bf16 *x0 = reinterpret_cast<__bf16 *>(cnn_smem + wv * kWaveBytes);
-    __bf16 *ha = x0 + kCnnRows * 24;
-    __bf16 *hb = ha + kCnnRows * 32;
+    __bf16 *hb = x0 + kWaveBuf;
     WaveFrag fr;
     load_wave_frag(fr, model, lane);
     wave_clear(x0, lane);
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) void k_cnn_windows(const uint8_t *mo
             const float v = (n >= lo && n < hi) ? ((float)src[i] - 128.0f) * (1.0f / 64.0f) : 0.0f;
             x0[(n + kCnnGuard) * 24 + 3 * line + ch] = to_bf16(v);
         }
-        wave_forward(fr, x0, ha, hb, lo, hi, lane, [&](int n, float z) {
+        wave_forward(fr, x0, hb, lo, hi, lane, [&](int n, float z) {
             if (n >= kCnnHalo && n < kCnnWin - kCnnHalo)
                 z_out[(int64_t)wi * kCnnOut + n - kCnnHalo] = z;
         });
@@ -497,8 +500,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) __attribute__((amdgpu_waves_per_eu(2
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     __bf16 *x0 = reinterpret_cast<__bf16 *>(cnn_smem + wv * kWaveBytes);
-    __bf16 *ha = x0 + kCnnRows * 24;
-    __bf16 *hb = ha + kCnnRows * 32;
+    __bf16 *hb = x0 + kWaveBuf;
     const int xcd = blockIdx.x & 7;
     const int per_xcd_groups = gridDim.x >> 3;
     const int first = xcd * a.per_xcd;
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(kCnnWaveBlock) __attribute__((amdgpu_waves_per_eu(2
             const int hi = L - start < kCnnWin ? L - start : kCnnWin;
             wave_sync();
             wave_gather(x0, frame, d.W, d.H, d.rs, horizontal, pos, L, start, lane);
-            wave_forward(fr, x0, ha, hb, lo, hi, lane, [&](int n, float z) {
+            wave_forward(fr, x0, hb, lo, hi, lane, [&](int n, float z) {
                 const int p = start + n;
                 if (n >= kCnnHalo && n < kCnnWin - kCnnHalo && p < L) {
                     const float sc = sigmoid(z);
