@@ -253,8 +253,9 @@ __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float
 }
 
 // Last convolution (32 -> 16) with the 1x1 layer folded in: z[n] for the
-// wave's 128 positions, returned to lanes 0..15 one n-tile at a time through
-// `emit(n, z)`.
+// wave's 128 positions, handed out in two calls of `emit(n, z)` in which
+// every lane holds one position (lane group q takes position tile q of the
+// group), so the sigmoid and the argmax that follow run on full waves.
 template <typename Emit>
 __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *X, int lo, int hi,
                                               int lane, Emit emit)
@@ -279,6 +280,8 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w4[0][ks], bv[t], acc[t], 0, 0,
                                                                  0);
         }
+        static_assert(kNB == 4, "one position tile per lane group");
+        float mine = 0.0f;
 #pragma unroll
         for (int t = 0; t < kNB; ++t) {
             const int n = n0 + 16 * t;
@@ -291,14 +294,15 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
             }
             part += __shfl_xor(part, 16, 64);
             part += __shfl_xor(part, 32, 64);
-            if (lane < 16)
-                emit(n, fr.b5 + part);
+            mine = (lane >> 4) == t ? part : mine;
         }
+        emit(n0 + 16 * (lane >> 4), fr.b5 + mine);
     }
 }
 
 // Logits of one window whose input rows are in w.x0: all 128 positions, in
-// 8 calls of emit (positions outside the strip carry unspecified values).
+// 2 calls of emit, one position per lane (positions outside the strip carry
+// unspecified values).
 template <typename Emit>
 __device__ __forceinline__ void wave_forward(const WaveFrag &fr, __bf16 *A, __bf16 *B, int lo,
                                              int hi, int lane, Emit emit)
