@@ -131,17 +131,42 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     torch.cuda.synchronize()
     kt = est.profile_end()
     G = 10 if K % 10 == 0 else 1
-    graphs = [est.capture(r, lp, uids, out=out, calls=G) for r in resident]
-    for g in graphs:
-        g.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K // G):
-        graphs[i % len(graphs)].launch()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for g in graphs:
-        g.close()
+    # as in the headline step: `args.inflight` contexts (each with the model,
+    # its own buffers, output and stream) take the graphs in turn
+    n_inflight = max(1, args.inflight)
+    extra = []
+    for _ in range(n_inflight - 1):
+        e = api.Estimator(0)
+        e.set_model(train_scorer.load_model(path))
+        extra.append(e)
+    ests = [est] + extra
+    outs = [out] + [torch.empty_like(out) for _ in extra]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in extra]
+
+    def graph_region(n):
+        graphs = [[ests[k].capture(r, lp, uids, out=outs[k], calls=G) for r in resident]
+                  for k in range(n)]
+        for k in range(n):
+            for g in graphs[k]:
+                g.launch(streams[k])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(K // G):
+            k = i % n
+            graphs[k][(i // n) % len(resident)].launch(streams[k])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for gs in graphs:
+            for g in gs:
+                g.close()
+        return dt
+
+    elapsed_one = graph_region(1)
+    elapsed = graph_region(n_inflight) if n_inflight > 1 else elapsed_one
+    ref = est.estimate_area(resident[0], lp, uids).raw
+    identical = all(torch.equal(e.estimate_area(resident[0], lp, uids).raw, ref) for e in extra)
+    for e in extra:
+        e.close()
     lat = []
     for i in range(min(args.latency_calls, 100)):
         t1 = time.perf_counter()
@@ -165,7 +190,9 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
                      "learned_fallback": evaluate.accuracy(est, fr, sp, lp)}
     return {
         "value": B * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
-        "steps": K, "timing": f"HIP graphs of {G} calls",
+        "steps": K, "timing": f"HIP graphs of {G} calls, {n_inflight} batches in flight",
+        "inflight": {"batches": n_inflight, "results_identical": bool(identical)},
+        "one_in_flight_value": B * K / elapsed_one,
         "scorer": "learned 1-D CNN (BF16 MFMA), handcrafted fallback below 0.5 inlier fraction",
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "kernels": {"k_cnn_strips": {"avg_us": cnn_ms * 1e3},

@@ -1,11 +1,12 @@
 """Several batches in flight: independent contexts, each with its own plan
 buffers, output and HIP stream, running the path concurrently on one GPU
-(eager calls and captured graphs, taking turns) give bit-identical results to
-one context running alone, on every call."""
+(eager calls and captured graphs, taking turns; the handcrafted scorer under
+both schedules and the learned scorer with its fallback) give bit-identical
+results to one context running alone, on every call."""
 import numpy as np
 import pytest
 
-from paper_2210_14771_amd import api, synth
+from paper_2210_14771_amd import api, synth, train_scorer
 
 from gpu_helpers import say
 
@@ -22,22 +23,30 @@ def torch_dev():
     return torch
 
 
-@pytest.mark.parametrize("schedule", ["split", "fused"])
+def _estimator(schedule, learned):
+    e = api.Estimator(0)
+    e.set_option("schedule", "split" if learned else schedule)
+    if learned:
+        e.set_model(train_scorer.load_model())
+    return e
+
+
+@pytest.mark.parametrize("schedule", ["split", "fused", "learned"])
 def test_two_contexts_two_streams(torch_dev, schedule):
     torch = torch_dev
+    learned = schedule == "learned"
     frames, _ = synth.make_batch(synth.SMALL_640x480, 8)
     batches = [torch.from_numpy(frames).cuda(),
                torch.from_numpy(np.ascontiguousarray(frames[:, ::-1])).cuda()]
-    params = api.default_params(**KW)
+    # the learned scorer with the handcrafted fallback: both paths per call
+    params = (api.default_params(**KW, scorer=1, fallback_inlier_frac=0.5) if learned
+              else api.default_params(**KW))
     uids = list(range(len(frames)))
-    say(f"in flight: schedule {schedule}")
-    ref_est = api.Estimator(0)
-    ref_est.set_option("schedule", schedule)
+    say(f"in flight: {schedule}")
+    ref_est = _estimator(schedule, learned)
     refs = [ref_est.estimate_area(b, params, uids).raw.cpu() for b in batches]
     ref_est.close()
-    ests = [api.Estimator(0), api.Estimator(0)]
-    for e in ests:
-        e.set_option("schedule", schedule)
+    ests = [_estimator(schedule, learned), _estimator(schedule, learned)]
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     # eager: 2 x 6 calls alternating over the two contexts, each into its own output
     outs = [[torch.empty((len(frames), 8), dtype=torch.int32, device="cuda") for _ in range(6)]
