@@ -269,11 +269,31 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
     const int n_pass = uniform((Lmax + span - 1) / span);
     const int sg_last = a.sg_len - 1;
     const uint8_t *t0 = c.tile, *t1 = c.tile + LP, *t2 = c.tile + 2 * LP;
+    const int dir = half == 0 ? 1 : -1;
 
     uint32_t carry = 0;
     uint64_t best = 0;
     for (int pass = 0; pass < n_pass; ++pass) {
         const int k0 = pass * span + lt * chunk;
+        // Columns are read once each, sliding along: column c holds pixel
+        // k0 + c - 1 of the half (position clamped to the line, which
+        // replicates the end pixels as the Sobel operator needs) as the
+        // column sum t0 + 2 t1 + t2, the difference t2 - t0 and t1.  Pixel j
+        // sits at column j + 1; its neighbours along the line at columns j and
+        // j + 2 (in the second half the pixels at i + 1 and i - 1, hence the
+        // sign `dir`).
+        auto column = [&](int cc, int &S_, int &D_, uint32_t &M_) {
+            int x = half == 0 ? k0 + cc - 1 : L - k0 - cc;
+            x = x < 0 ? 0 : (x > L - 1 ? L - 1 : x);
+            const int a0 = t0[x], a1 = t1[x], a2 = t2[x];
+            S_ = a0 + 2 * a1 + a2;
+            D_ = a2 - a0;
+            M_ = (uint32_t)a1;
+        };
+        int S0, S1, D0, D1;
+        uint32_t M0, M1;
+        column(0, S0, D0, M0);
+        column(1, S1, D1, M1);
         float part[kChunk];
         uint32_t lum[kChunk];
         uint32_t tmax = 0;
@@ -281,16 +301,20 @@ __device__ void strip_work(const StripArgs &a, const StripLds &c, int f, int s)
         for (int j = 0; j < kChunk; ++j) {
             part[j] = 0.0f;
             lum[j] = 0;
+            int S2, D2;
+            uint32_t M2;
+            column(j + 2, S2, D2, M2);
+            const int along = dir * (S2 - S0);
+            const int across = D0 + 2 * D1 + D2;
+            const uint32_t y1 = M1;
+            S0 = S1;
+            S1 = S2;
+            D0 = D1;
+            D1 = D2;
+            M1 = M2;
             const int k = k0 + j;
             if (j < chunk && k < Lh) {
                 const int i = half == 0 ? k : L - 1 - k;
-                const int im = i > 0 ? i - 1 : 0;
-                const int ip = i < L - 1 ? i + 1 : L - 1;
-                const int along = ((int)t0[ip] + 2 * (int)t1[ip] + (int)t2[ip])
-                                  - ((int)t0[im] + 2 * (int)t1[im] + (int)t2[im]);
-                const int across = ((int)t2[im] + 2 * (int)t2[i] + (int)t2[ip])
-                                   - ((int)t0[im] + 2 * (int)t0[i] + (int)t0[ip]);
-                const uint32_t y1 = t1[i];
                 part[j] = horizontal
                               ? grad_angle_score(along, across, i, pos, d.W, d.H, c.sg, sg_last, c.st)
                               : grad_angle_score(across, along, pos, i, d.W, d.H, c.sg, sg_last, c.st);
