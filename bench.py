@@ -303,6 +303,26 @@ def cpu_baseline(frames, kw, target_cpu_s: float):
                       f"passes ({n} frame estimates, {wall:.1f} s wall, {threads} threads)"}
 
 
+def copy_bandwidth(dev, mib: int = 1024, reps: int = 20) -> dict:
+    """A plain device-to-device copy on the same GPU (bytes read + written
+    per second): the practical HBM ceiling beside the published 8 TB/s."""
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"value": 2 * (mib << 20) / (ms * 1e-3) / 1e9, "unit": "GB/s",
+            "what": f"torch copy_ of {mib} MiB, read + write bytes, mean of {reps}"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -524,6 +544,7 @@ def main():
     if mixed is not None:
         line["mixed_512"] = mixed
     line["env"] = run_environment(params)
+    line["hbm_copy_gbps"] = copy_bandwidth(dev)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(frames, kw, args.cpu_seconds)
