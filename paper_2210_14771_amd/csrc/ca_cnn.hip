@@ -203,16 +203,46 @@ __device__ __forceinline__ void wave_sync()
 // channel tile per B fragment.
 constexpr int kNB = 4;
 
+// Element offset of channels c .. c + 7 (c a multiple of 4) of row `row` in
+// a wave's position-major buffer of C channels.  With 32 or 16 channels the
+// 16-byte chunks of a row are permuted by row (XOR with bits of the row
+// index) so that the 16 lanes of one LDS pass, which read or write 16
+// consecutive rows at the same channel, hit 16 distinct groups of 4 banks
+// instead of 4 (32 channels) or 8 (16 channels); 24-channel rows already do.
+// The permutation depends only on row / 4 mod 4 (row / 8 mod 2), so shifting
+// by whole 16-row tiles keeps it.
+template <int C>
+__device__ __forceinline__ int act_off(int row, int c)
+{
+    static_assert(C == 16 || C == 24 || C == 32, "buffer width");
+    if (C == 32)
+        return row * 32 + ((((c >> 3) ^ (row >> 2)) & 3) << 3) + (c & 7);
+    if (C == 16)
+        return row * 16 + ((((c >> 3) ^ (row >> 3)) & 1) << 3) + (c & 7);
+    return row * 24 + c;
+}
+
 template <int CIN, int COUT, int MT, int KS>
 __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float (&bias)[MT][4],
                                           const __bf16 *X, __bf16 *Y, int lo, int hi, int lane)
 {
     typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
     const int kq = 8 * (lane >> 4);
+    // this lane's B-fragment offsets (K index 32 ks + kq = tap * CIN + c) and
+    // output offsets, for position lane % 16; tiles 16 rows on add t 16 CIN
+    int boff[KS], yoff[MT];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = 32 * ks + kq;
+        boff[ks] = act_off<CIN>((lane & 15) + kCnnGuard - 2 + k / CIN, k % CIN);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        yoff[mt] = act_off<COUT>((lane & 15) + kCnnGuard, mt * 16 + 4 * (lane >> 4));
 #pragma unroll 1
     for (int g = 0; g < kCnnWin / 16 / kNB; ++g) {
         const int n0 = g * kNB * 16 + (lane & 15);
-        const __bf16 *b0 = X + (n0 + kCnnGuard - 2) * CIN + kq;
+        const __bf16 *b0 = X + g * kNB * 16 * CIN;
         // accumulators start at the bias
         f32x4 acc[kNB][MT];
 #pragma unroll
@@ -225,7 +255,7 @@ __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float
             bf16x8 bv[kNB];
 #pragma unroll
             for (int t = 0; t < kNB; ++t)
-                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * CIN + 32 * ks);
+                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * CIN + boff[ks]);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -245,8 +275,7 @@ __device__ __forceinline__ void wave_conv(const bf16x8 (&A)[MT][KS], const float
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     o[j] = to_bf16(__builtin_amdgcn_fmed3f(acc[t][mt][j], 0.0f, top));
-                *reinterpret_cast<bf16x4 *>(Y + (n + kCnnGuard) * COUT + mt * 16 + 4 * (lane >> 4)) =
-                    o;
+                *reinterpret_cast<bf16x4 *>(Y + (n - (lane & 15)) * COUT + yoff[mt]) = o;
             }
         }
     }
@@ -261,10 +290,14 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
                                               int lane, Emit emit)
 {
     const int kq = 8 * (lane >> 4);
+    int boff[5];
+#pragma unroll
+    for (int ks = 0; ks < 5; ++ks)
+        boff[ks] = act_off<32>((lane & 15) + kCnnGuard - 2 + ks, kq);
 #pragma unroll 1
     for (int g = 0; g < kCnnWin / 16 / kNB; ++g) {
         const int n0 = g * kNB * 16 + (lane & 15);
-        const __bf16 *b0 = X + (n0 + kCnnGuard - 2) * 32 + kq;
+        const __bf16 *b0 = X + g * kNB * 16 * 32;
         f32x4 acc[kNB];
 #pragma unroll
         for (int t = 0; t < kNB; ++t)
@@ -274,7 +307,7 @@ __device__ __forceinline__ void wave_conv_out(const WaveFrag &fr, const __bf16 *
             bf16x8 bv[kNB];
 #pragma unroll
             for (int t = 0; t < kNB; ++t)
-                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * 32 + 32 * ks);
+                bv[t] = *reinterpret_cast<const bf16x8 *>(b0 + t * 16 * 32 + boff[ks]);
 #pragma unroll
             for (int t = 0; t < kNB; ++t)
                 acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w4[0][ks], bv[t], acc[t], 0, 0,
