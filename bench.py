@@ -3,9 +3,10 @@
 One step = one call of the whole hot path (strip scoring, candidate
 selection, RANSAC with refits, best-circle selection) on a batch of 64
 synthetic 1920x1080 RGB frames already resident in HBM.  The timed steps
-replay captured HIP graphs with two batches in flight (two contexts on two
-HIP streams taking turns, so one batch's FP64 RANSAC overlaps the next
-batch's strip loads); the same steps with one batch in flight, and eager
+replay captured HIP graphs with four batches in flight (four contexts on
+four HIP streams taking turns, so one batch's FP64 RANSAC overlaps other
+batches' strip loads, and the strip loads of several batches together keep
+more DRAM pages busy); the same steps with one batch in flight, and eager
 calls, are reported beside.  Prints one JSON
 line with frames/s, per-call latency percentiles, the dominant kernel's
 roofline position (kernel time from HIP events recorded inside the library
@@ -46,7 +47,7 @@ def parse():
                          "the batch")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=4,
                     help="batches in flight in the timed region: contexts, each with its own "
                          "plan buffers, output and HIP stream, taking the graphs in turn")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")

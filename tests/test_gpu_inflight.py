@@ -32,7 +32,7 @@ def _estimator(schedule, learned):
 
 
 @pytest.mark.parametrize("schedule", ["split", "fused", "learned"])
-def test_two_contexts_two_streams(torch_dev, schedule):
+def test_four_contexts_four_streams(torch_dev, schedule):
     torch = torch_dev
     learned = schedule == "learned"
     frames, _ = synth.make_batch(synth.SMALL_640x480, 8)
@@ -46,31 +46,33 @@ def test_two_contexts_two_streams(torch_dev, schedule):
     ref_est = _estimator(schedule, learned)
     refs = [ref_est.estimate_area(b, params, uids).raw.cpu() for b in batches]
     ref_est.close()
-    ests = [_estimator(schedule, learned), _estimator(schedule, learned)]
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    # eager: 2 x 6 calls alternating over the two contexts, each into its own output
+    n = 4
+    ests = [_estimator(schedule, learned) for _ in range(n)]
+    streams = [torch.cuda.Stream() for _ in range(n)]
+    # eager: n x 6 calls taking turns over the contexts, each into its own output
     outs = [[torch.empty((len(frames), 8), dtype=torch.int32, device="cuda") for _ in range(6)]
-            for _ in range(2)]
+            for _ in range(n)]
     torch.cuda.synchronize()
     for i in range(6):
-        for k in range(2):
+        for k in range(n):
             ests[k].estimate_area(batches[(i + k) % 2], params, uids, out=outs[k][i],
                                   stream=streams[k])
     torch.cuda.synchronize()
     for i in range(6):
-        for k in range(2):
+        for k in range(n):
             assert torch.equal(outs[k][i].cpu(), refs[(i + k) % 2]), (i, k)
     # graphs: each context replays its own graph on its own stream
-    gouts = [torch.empty((len(frames), 8), dtype=torch.int32, device="cuda") for _ in range(2)]
-    graphs = [ests[k].capture(batches[k], params, uids, out=gouts[k], calls=3) for k in range(2)]
+    gouts = [torch.empty((len(frames), 8), dtype=torch.int32, device="cuda") for _ in range(n)]
+    graphs = [ests[k].capture(batches[k % 2], params, uids, out=gouts[k], calls=3)
+              for k in range(n)]
     for rep in range(3):
         for o in gouts:
             o.zero_()
-        for k in range(2):
+        for k in range(n):
             graphs[k].launch(streams[k])
         torch.cuda.synchronize()
-        for k in range(2):
-            assert torch.equal(gouts[k].cpu(), refs[k]), (rep, k)
+        for k in range(n):
+            assert torch.equal(gouts[k].cpu(), refs[k % 2]), (rep, k)
     for g in graphs:
         g.close()
     for e in ests:
