@@ -28,6 +28,10 @@
  *     Calls on one context may target different streams; the context
  *     serialises its own scratch use by enqueuing on the given stream, so
  *     calls on two different streams of one context must not overlap.
+ *   - Contexts are independent (each owns its buffers): calls of several
+ *     contexts on one device may overlap on different streams.  Keeping a
+ *     few batches in flight that way lets one batch's RANSAC (FP64 ALU) run
+ *     beside other batches' strip loads (HBM).
  */
 #ifndef CONTENTAREA_H
 #define CONTENTAREA_H
