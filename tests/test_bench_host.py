@@ -1,0 +1,73 @@
+"""Host-side pieces of bench.py, on the CPU: the one-GPU guard, the
+algorithmic byte and flop counts its rooflines divide by, and the rule that
+a committed traffic summary counts only for the kernel source it was taken
+from."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_strip_bytes_per_frame():
+    # three rows of RGB per horizontal strip, nine bytes per row per vertical strip
+    assert bench.strip_bytes_per_frame(1920, 1080, 32, 32) == 32 * 3 * 5760 + 32 * 1080 * 9
+    assert bench.strip_bytes_per_frame(1920, 1080, 32, 32) == 864_000
+    assert bench.strip_bytes_per_frame(640, 480, 16, 16) == 161_280
+    assert bench.strip_bytes_per_frame(640, 480, 16, 0) == 16 * 3 * 1920
+
+
+def test_learned_flops_per_frame():
+    # 12,176 multiply-adds per strip position (four width-5 convolutions and
+    # the 1x1 layer), every position of 32 rows and 32 columns
+    macs = 5 * (24 * 16 + 16 * 32 + 32 * 32 + 32 * 16) + 16
+    assert macs == 12_176
+    assert bench.cnn_flops_per_frame(1920, 1080, 32, 32) == 2.0 * macs * (32 * 1920 + 32 * 1080)
+
+
+def test_ransac_flops_counts_frames_with_three_points():
+    assert bench.ransac_flops([0, 2], 1024, 3) == 0.0
+    assert bench.ransac_flops([100], 1024, 3) == 1024 * 100 * (3 * 23 + 9)
+
+
+def _fake_tree(tmp_path, source: bytes, recorded_sha: str):
+    src = tmp_path / "paper_2210_14771_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "ca_kernels.hip").write_bytes(source)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "k_strips_64x1080p_hbm_traffic.md").write_text(
+        "traffic_bytes_per_launch k_strips 123456\n"
+        f"source_sha256_prefix {recorded_sha}\n")
+
+
+def test_traffic_summary_counts_only_for_its_source(tmp_path, monkeypatch):
+    source = b"// kernels\n"
+    sha = hashlib.sha256(source).hexdigest()[:16]
+    _fake_tree(tmp_path, source, sha)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k_strips") == 123456
+    (tmp_path / "paper_2210_14771_amd" / "csrc" / "ca_kernels.hip").write_bytes(source + b"x")
+    assert bench.measured_traffic("k_strips") is None
+
+
+def test_traffic_summary_missing(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k_strips") is None
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-q"]))
