@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU work of the oracle sample")
-    ap.add_argument("--batches", type=int, default=2, help="distinct resident batches rotated")
+    ap.add_argument("--batches", type=int, default=3, help="distinct resident batches rotated")
     ap.add_argument("--schedule", choices=["auto", "fused", "split"], default="auto",
                     help="auto: the schedule and strip tiles ca_autotune measures fastest for "
                          "the batch")
@@ -59,6 +59,8 @@ def parse():
                     help="device-rendered hard 1080p frames for the accuracy comparison")
     ap.add_argument("--mixed-steps", type=int, default=20,
                     help="timed graph replays of the 512-frame uneven batch (0: skip)")
+    ap.add_argument("--small-steps", type=int, default=20,
+                    help="timed graph launches (100 calls each) of the 8 x 640x480 case (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -206,6 +208,41 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
                                          "border noise sigma 2-12, specular blobs and white "
                                          "text in the border"),
     }
+
+
+def small_section(args):
+    """The small case (8 x 640x480, 16+16 strips, 256 attempts): launch-bound,
+    so its steady state is taken from one HIP graph of 100 back-to-back calls."""
+    import torch
+    from paper_2210_14771_amd import api, synth
+    if args.small_steps <= 0:
+        return None
+    wl = synth.SMALL_640x480
+    frames, _ = synth.make_batch(wl)
+    dev = torch.from_numpy(frames).cuda()
+    kw = dict(n_hstrips=wl.n_hstrips, n_vstrips=wl.n_vstrips, ransac_attempts=wl.attempts)
+    params = api.default_params(**kw)
+    uids = list(range(len(frames)))
+    est = api.Estimator(0)
+    est.set_option("schedule", "auto")
+    est.autotune(dev, params, uids, reps=20)
+    out = torch.empty((len(frames), 8), dtype=torch.int32, device="cuda")
+    g = est.capture(dev, params, uids, out=out, calls=100)
+    g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.small_steps):
+        g.launch()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    est.close()
+    calls = 100 * args.small_steps
+    return {"workload": f"plain pipeline, {len(frames)} x {wl.width}x{wl.height} frames per call, "
+                        f"{kw['n_hstrips']}+{kw['n_vstrips']} strips, {kw['ransac_attempts']} "
+                        f"RANSAC attempts, HIP graphs of 100 back-to-back calls",
+            "value": len(frames) * calls / dt, "unit": "frames/s", "us_per_call": dt / calls * 1e6,
+            "calls": calls, "schedule": est.last_tuned_schedule}
 
 
 def mixed_section(args, est, kw):
@@ -441,6 +478,17 @@ def main():
 
     elapsed_one = graph_region(1)
     elapsed = graph_region(n_inflight) if n_inflight > 1 else elapsed_one
+    # warm case: every step on the first resident batch (its strip lines may
+    # stay in the Infinity Cache between steps), one in flight
+    g_warm = est.capture(resident[0], params, uids, out=out, calls=G)
+    g_warm.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K // G):
+        g_warm.launch()
+    torch.cuda.synchronize()
+    elapsed_warm = time.perf_counter() - t0
+    g_warm.close()
     for e in ests:
         e.device_status()
     # every context gives the same results
@@ -526,6 +574,8 @@ def main():
         "inflight": {"batches": n_inflight, "results_identical": bool(inflight_identical)},
         "one_in_flight_value": B * K / elapsed_one,
         "one_in_flight_ms_per_step": elapsed_one / K * 1e3,
+        "warm_value": B * K / elapsed_warm,
+        "warm_note": "one resident batch for every step, one in flight",
         "eager_value": B * K / elapsed_eager,
         "eager_ms_per_step": elapsed_eager / K * 1e3,
         "schedule": schedule_used,
@@ -544,6 +594,10 @@ def main():
     mixed = mixed_section(args, est, kw)
     if mixed is not None:
         line["mixed_512"] = mixed
+    print("# small case", file=sys.stderr, flush=True)
+    small = small_section(args)
+    if small is not None:
+        line["small_640x480"] = small
     line["env"] = run_environment(params)
     line["hbm_copy_gbps"] = copy_bandwidth(dev)
     if not args.no_cpu_baseline:
