@@ -236,13 +236,14 @@ def small_section(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     g.close()
+    schedule = est.last_tuned_schedule
     est.close()
     calls = 100 * args.small_steps
     return {"workload": f"plain pipeline, {len(frames)} x {wl.width}x{wl.height} frames per call, "
                         f"{kw['n_hstrips']}+{kw['n_vstrips']} strips, {kw['ransac_attempts']} "
                         f"RANSAC attempts, HIP graphs of 100 back-to-back calls",
             "value": len(frames) * calls / dt, "unit": "frames/s", "us_per_call": dt / calls * 1e6,
-            "calls": calls, "schedule": est.last_tuned_schedule}
+            "calls": calls, "schedule": schedule}
 
 
 def mixed_section(args, est, kw):
