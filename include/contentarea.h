@@ -61,7 +61,10 @@ typedef struct {
     int32_t width, height;   /* pixels, each in [16, CA_MAX_EXTENT] */
     int32_t row_stride;      /* bytes between the starts of two rows, >= 3 * width */
     int32_t pixel_stride;    /* bytes between pixels; must be 3 */
-    int64_t byte_offset;     /* first byte of the frame relative to `frames_dev`, >= 0 */
+    int64_t byte_offset;     /* first byte of the frame relative to `frames_dev`, >= 0;
+                                bytes [byte_offset, byte_offset + (height - 1) * row_stride
+                                + 3 * width) must lie in the caller's allocation (the
+                                library cannot see device extents and reads only these) */
     uint64_t frame_uid;      /* identifies the frame to the RANSAC sampler: the
                                 triples depend on (seed, frame_uid, attempt) only,
                                 never on the frame's position in the batch */
