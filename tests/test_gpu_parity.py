@@ -81,18 +81,26 @@ def test_hd_workload_parity(torch_dev, est, hd_batch):
     assert bits[0] == bits[1]
 
 
+WIDE = dict(n_hstrips=64, n_vstrips=64, ransac_attempts=256, t_ps=0.0, t_px=0)
+
+
 @pytest.fixture(scope="module")
 def wide_batch():
-    return np.stack([synth.make_frame(synth.HD_1080p, 300 + i, 8192, 2048)[0] for i in range(2)])
+    return np.stack([synth.make_frame(synth.HD_1080p, 310 + i, 16384, 512)[0] for i in range(2)])
 
 
 def test_large_extent_parity(torch_dev, est, wide_batch):
-    # 8192 x 2048 frames: once 8 or more points are kept, the centred moment
-    # products of the refit reach 2^52, so they are formed in int64 rather
-    # than float64; both forms must agree with the oracle bit for bit
-    g, r, bits = _full_parity(torch_dev, est, wide_batch, dict(HD, ransac_attempts=256),
-                              uids=[300, 301])
-    assert min(int(x["n_points"]) for x in r) >= 8
+    # 16384 x 512 frames keeping all 256 candidates (no score or edge filter):
+    # n^2 max(U, V) (U^2 + V^2) is 8 times 2^52, so the refits form the
+    # centred moment sums in int64 rather than float64; both forms must agree
+    # with the oracle bit for bit
+    g, r, bits = _full_parity(torch_dev, est, wide_batch, WIDE, uids=[310, 311])
+    W, H = 16384, 512
+    U, V = W // 2, H // 2
+    for x in r:
+        n = int(x["n_points"])
+        assert n == 256
+        assert float(n) * n * max(U, V) * (U * U + V * V) >= 2.0 ** 52
     assert bits[0] == bits[1]
 
 
