@@ -372,6 +372,14 @@ def _tiny_frame(seed):
     return fr[0][::5, ::5].copy(), specs[0]      # 128 x 96
 
 
+def _py_keep(cx, cy, r, W, H, p):
+    """Section 2.2.5's limits stated with Euclidean distances: radius within
+    [r_min, r_max] times the width, centre within d_max times the width of the
+    frame centre ((W - 1)/2, (H - 1)/2) in pixel-index coordinates."""
+    return (p.r_min * W <= r <= p.r_max * W
+            and math.hypot(cx - (W - 1) / 2, cy - (H - 1) / 2) <= p.d_max * W)
+
+
 def _py_attempt(u, v, sq, t, K, tri):
     """Independent statement of one attempt with numpy: lstsq fits and
     Euclidean distances (|d - r| <= t) instead of the oracle's squared band."""
@@ -396,25 +404,48 @@ def _py_attempt(u, v, sq, t, K, tri):
     return int(sq[m].sum()), int(m.sum()), c, r
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_ransac_attempts_match_independent_numpy(seed):
+def _split_value(vals):
+    """A threshold halfway between two neighbouring distinct values near the
+    middle of `vals`, so that both sides of a limit hold many attempts and
+    none sits on it."""
+    v = np.unique(np.round(np.asarray(vals, dtype=np.float64), 9))
+    k = max(1, len(v) // 2)
+    return float((v[k - 1] + v[k]) / 2)
+
+
+@pytest.mark.parametrize("seed,limit", [(s, "table_a1") for s in (0, 1, 2)]
+                         + [(s, lim) for s in (1, 4, 5) for lim in ("r_min", "r_max", "d_max")])
+def test_ransac_attempts_match_independent_numpy(seed, limit):
     frame, _ = _tiny_frame(seed)
+    H, W = frame.shape[:2]
     p = oracle.params(n_hstrips=4, n_vstrips=3, sampler=1, attempts=4096, t_px=1)
     res, pts = oracle.estimate(frame, p, uid=seed, with_points=True)
     k = pts[pts["keep"] == 1]
     n = len(k)
     assert n >= 6
-    H, W = frame.shape[:2]
-    att = oracle.ransac_attempts(k["x"], k["y"], (k["score"] * np.float32(2 ** 24)).astype(np.uint32),
-                                 W, H, seed, p)
     u = k["x"].astype(np.int64) - W // 2
     v = k["y"].astype(np.int64) - H // 2
     sq = (k["score"] * np.float32(2 ** 24)).astype(np.uint64)
+    refs = {tri: _py_attempt(u, v, sq, 3.0, 3, tri)
+            for tri in itertools.combinations(range(n), 3)}
+    circles = [(c[0] + W // 2, c[1] + H // 2, r) for ref in refs.values() if ref is not None
+               for _, _, c, r in [ref]]
+    if limit in ("r_min", "r_max"):
+        # one radius limit cuts the attempts' radii in two, the other stays open
+        cut = _split_value([r for _, _, r in circles]) / W
+        p.r_min, p.r_max = (cut, 10.0) if limit == "r_min" else (0.0, cut)
+        p.d_max = 10.0
+    elif limit == "d_max":
+        p.r_min, p.r_max = 0.0, 10.0
+        p.d_max = _split_value([math.hypot(x - (W - 1) / 2, y - (H - 1) / 2)
+                                for x, y, _ in circles]) / W
+    att = oracle.ransac_attempts(k["x"], k["y"], sq.astype(np.uint32), W, H, seed, p)
     mismatches = 0
+    statuses = {0: 0, 1: 0, 2: 0}
     for a, tri in enumerate(itertools.combinations(range(n), 3)):
         o = att[a]
         assert (o["i0"], o["i1"], o["i2"]) == tri
-        ref = _py_attempt(u, v, sq, 3.0, 3, tri)
+        ref = refs[tri]
         if ref is None:
             mismatches += int(o["status"] != 0)
             continue
@@ -424,8 +455,15 @@ def test_ransac_attempts_match_independent_numpy(seed):
             continue
         assert abs(o["cx"] - (c[0] + W // 2)) < 1e-6 and abs(o["cy"] - (c[1] + H // 2)) < 1e-6
         assert abs(math.sqrt(o["r2"]) - r) < 1e-6
+        # kept (2) or outside the radius / centre limits (1)
+        keep = _py_keep(c[0] + W // 2, c[1] + H // 2, r, W, H, p)
+        statuses[int(o["status"])] += 1
+        assert o["status"] == (2 if keep else 1), (a, tri)
     # only points sitting on a band edge within rounding may disagree
     assert mismatches <= max(1, math.comb(n, 3) // 200)
+    # a split limit leaves both outcomes among the compared attempts
+    if limit != "table_a1":
+        assert statuses[1] > 0 and statuses[2] > 0, statuses
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
