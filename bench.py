@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU work of the oracle sample")
-    ap.add_argument("--batches", type=int, default=3, help="distinct resident batches rotated")
+    ap.add_argument("--batches", type=int, default=5,
+                    help="distinct resident batches rotated (more than --inflight, so calls in "
+                         "flight together read different batches)")
     ap.add_argument("--schedule", choices=["auto", "fused", "split"], default="auto",
                     help="auto: the schedule and strip tiles ca_autotune measures fastest for "
                          "the batch")
@@ -66,6 +68,23 @@ def parse():
     return ap.parse_args()
 
 
+def graph_calls(steps: int, wanted: int, cycle: int) -> int:
+    """Calls per captured graph: the largest G <= wanted dividing `steps`
+    that still leaves steps // G >= cycle launches (every context and every
+    resident batch used); 1 when no such G exists."""
+    for g in range(min(wanted, steps), 0, -1):
+        if steps % g == 0 and steps // g >= cycle:
+            return g
+    return 1
+
+
+def rotation_used(launches: int, contexts: int, batches: int) -> dict:
+    """Contexts and resident batches a run of `launches` graph launches
+    actually touches when launch i goes to context i % contexts and reads
+    batch i % batches."""
+    return {"contexts": min(contexts, launches), "batches": min(batches, launches)}
+
+
 def strip_bytes_per_frame(w: int, h: int, n_h: int, n_v: int) -> int:
     """Bytes the method must read: 3 full rows per horizontal strip and
     3 pixels of every row per vertical strip (RGB, 3 bytes per pixel)."""
@@ -73,9 +92,19 @@ def strip_bytes_per_frame(w: int, h: int, n_h: int, n_v: int) -> int:
 
 
 def ransac_flops(n_points, attempts: int, refine: int) -> float:
-    """FP64 operations of the inlier passes: per point and refit pass the
-    squared distance (2 sub, 2 mul, 1 add) and 9 moment FMAs (18 flops);
-    per point in the final pass the distance and 2 FMAs (4 flops)."""
+    """FP64 operations the method itself asks for in the inlier passes: per
+    attempt, point and pass (K refits and the final count) the squared
+    distance to the centre (2 sub, 2 mul, 1 add); the band test is two
+    compares and the moment sums over inliers are integer additions, so
+    neither is counted."""
+    return float(sum(attempts * n * (refine + 1) * 5 for n in n_points if n >= 3))
+
+
+def ransac_issued_flops(n_points, attempts: int, refine: int) -> float:
+    """FP64 operations the kernel issues for the same passes: per point and
+    refit pass the squared distance (5) and 9 moment FMAs accumulating the
+    integer sums exactly in float64 (18), masked rather than branched; per
+    point in the final pass the distance and 2 FMAs (9)."""
     return float(sum(attempts * n * (refine * 23 + 9) for n in n_points if n >= 3))
 
 
@@ -133,10 +162,10 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
         est.estimate_area(resident[i % len(resident)], lp_nofb, uids, out=out)
     torch.cuda.synchronize()
     kt = est.profile_end()
-    G = 10 if K % 10 == 0 else 1
     # as in the headline step: `args.inflight` contexts (each with the model,
-    # its own buffers, output and stream) take the graphs in turn
+    # its own buffers, output and stream) take the graph launches in turn
     n_inflight = max(1, args.inflight)
+    G = graph_calls(K, 10, n_inflight * len(resident))
     extra = []
     for _ in range(n_inflight - 1):
         e = api.Estimator(0)
@@ -145,6 +174,7 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     ests = [est] + extra
     outs = [out] + [torch.empty_like(out) for _ in extra]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in extra]
+    used = {}
 
     def graph_region(n):
         graphs = [[ests[k].capture(r, lp, uids, out=outs[k], calls=G) for r in resident]
@@ -155,13 +185,13 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(K // G):
-            k = i % n
-            graphs[k][(i // n) % len(resident)].launch(streams[k])
+            graphs[i % n][i % len(resident)].launch(streams[i % n])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         for gs in graphs:
             for g in gs:
                 g.close()
+        used[n] = rotation_used(K // G, n, len(resident))
         return dt
 
     elapsed_one = graph_region(1)
@@ -193,8 +223,12 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
                      "learned_fallback": evaluate.accuracy(est, fr, sp, lp)}
     return {
         "value": B * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
-        "steps": K, "timing": f"HIP graphs of {G} calls, {n_inflight} batches in flight",
-        "inflight": {"batches": n_inflight, "results_identical": bool(identical)},
+        "steps": K,
+        "timing": f"{K // G} launches of HIP graphs of {G} calls on "
+                  f"{used[n_inflight]['contexts']} contexts taking the launches in turn, over "
+                  f"{used[n_inflight]['batches']} distinct resident batches",
+        "inflight": dict(used[n_inflight], graph_calls=G, launches=K // G,
+                         results_identical=bool(identical)),
         "one_in_flight_value": B * K / elapsed_one,
         "scorer": "learned 1-D CNN (BF16 MFMA), handcrafted fallback below 0.5 inlier fraction",
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -323,22 +357,26 @@ def run_environment(params) -> dict:
             "seed": int(params.seed), "data_seed": "SeedSequence([2210_14771, config, frame])"}
 
 
-def cpu_baseline(frames, kw, target_cpu_s: float):
+def cpu_baseline(frames, kw, target_cpu_s: float, threads: int | None = None):
+    """The oracle on the host cores, on the headline frames: one pass to
+    size the sample, then enough passes for about target_cpu_s of CPU time."""
     import oracle
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
     p = oracle.params(n_hstrips=kw["n_hstrips"], n_vstrips=kw["n_vstrips"],
                       attempts=kw["ransac_attempts"])
+    sample = frames if threads > 1 else frames[:8]
     t0 = time.perf_counter()
-    oracle.estimate_batch(frames, p, threads=threads)
+    oracle.estimate_batch(sample, p, threads=threads)
     t1 = time.perf_counter() - t0
     reps = max(1, min(50, math.ceil(target_cpu_s / max(t1 * threads, 1e-6))))
     t0 = time.perf_counter()
     for _ in range(reps):
-        oracle.estimate_batch(frames, p, threads=threads)
+        oracle.estimate_batch(sample, p, threads=threads)
     wall = time.perf_counter() - t0
-    n = reps * len(frames)
+    n = reps * len(sample)
     return {"value": n / wall, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(frames)} x {frames.shape[2]}x{frames.shape[1]} frames x {reps} "
+            "sample": f"{len(sample)} x {frames.shape[2]}x{frames.shape[1]} frames x {reps} "
                       f"passes ({n} frame estimates, {wall:.1f} s wall, {threads} threads)"}
 
 
@@ -452,14 +490,18 @@ def main():
     # and HIP stream) takes the graphs in turn, so one batch's RANSAC (FP64
     # ALU) overlaps the next one's strip loads (HBM); every batch still runs
     # the whole path.
-    G = args.graph_calls if K % args.graph_calls == 0 else 1
     n_inflight = max(1, args.inflight)
+    G = graph_calls(K, args.graph_calls, n_inflight * len(resident))
     extra = [make_estimator()[0] for _ in range(n_inflight - 1)]
     ests = [est] + extra
     outs = [out] + [torch.empty_like(out) for _ in extra]
     streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in extra]
+    used = {}
 
     def graph_region(n):
+        # launch i goes to context i % n and reads resident batch
+        # i % len(resident): with more batches than contexts, calls in flight
+        # together read distinct batches and every context meets every batch
         graphs = [[ests[k].capture(r, params, uids, out=outs[k], calls=G) for r in resident]
                   for k in range(n)]
         for k in range(n):
@@ -468,13 +510,13 @@ def main():
         torch.cuda.synchronize()
         t = time.perf_counter()
         for i in range(K // G):
-            k = i % n
-            graphs[k][(i // n) % len(resident)].launch(streams[k])
+            graphs[i % n][i % len(resident)].launch(streams[i % n])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         for gs in graphs:
             for g in gs:
                 g.close()
+        used[n] = rotation_used(K // G, n, len(resident))
         return dt
 
     elapsed_one = graph_region(1)
@@ -539,8 +581,15 @@ def main():
     if traffic:
         rl_strips["traffic_gbps"] = traffic / (strips_ms * 1e-3) / 1e9
     rl_strips["frac"] = rl_strips["achieved"] / rl_strips["peak"]
+    issued = ransac_issued_flops(res["n_points"], kw["ransac_attempts"], params.refine_iters)
     rl_ransac = {"bound": "alu", "achieved": flops / (ransac_ms * 1e-3) / 1e12,
-                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None}
+                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None,
+                 "flops_note": "the method's FP64 work: one squared distance (5 flops) per "
+                               "attempt, point and pass (3 refits + final count); band compares "
+                               "and integer moment sums not counted",
+                 "issued_tflops": issued / (ransac_ms * 1e-3) / 1e12,
+                 "issued_note": "FP64 operations the kernel issues (23 per point and refit "
+                                "pass, 9 per point in the final pass)"}
     rl_ransac["frac"] = rl_ransac["achieved"] / rl_ransac["peak"]
     roofline = dict(rl_ransac if dominant == "ransac" else rl_strips)
     roofline["kernel"] = {"fused": "k_fused", "strips": "k_strips", "ransac": "k_ransac"}[dominant]
@@ -569,10 +618,12 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "latency_note": "per call of 64 frames, each call synchronised on its own",
-        "timing": f"K steps replayed from HIP graphs of {G} calls, {n_inflight} batches in "
-                  f"flight ({n_inflight} contexts and HIP streams taking the graphs in turn); "
-                  f"one batch in flight and eager calls below",
-        "inflight": {"batches": n_inflight, "results_identical": bool(inflight_identical)},
+        "timing": f"K steps replayed from {K // G} launches of HIP graphs of {G} calls on "
+                  f"{used[n_inflight]['contexts']} contexts and HIP streams taking the launches "
+                  f"in turn, over {used[n_inflight]['batches']} distinct resident batches; one "
+                  f"batch in flight and eager calls below",
+        "inflight": dict(used[n_inflight], graph_calls=G, launches=K // G,
+                         results_identical=bool(inflight_identical)),
         "one_in_flight_value": B * K / elapsed_one,
         "one_in_flight_ms_per_step": elapsed_one / K * 1e3,
         "warm_value": B * K / elapsed_warm,
@@ -604,6 +655,7 @@ def main():
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(frames, kw, args.cpu_seconds)
+        line["cpu_baseline_1thread"] = cpu_baseline(frames, kw, args.cpu_seconds / 3, threads=1)
     if args.calibrate_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
         # scale the counters of the estimator's kernels to bytes

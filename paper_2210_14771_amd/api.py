@@ -37,6 +37,11 @@ def _as_params(params) -> N.Params:
     raise TypeError("params must be None, a dict or a Params")
 
 
+# one ca_result (32 bytes) as a numpy structured type
+RESULT_DTYPE = [("cx", "<f4"), ("cy", "<f4"), ("r", "<f4"), ("score", "<f4"),
+                ("inliers", "<i4"), ("n_points", "<i4"), ("valid", "<i4"), ("reason", "<i4")]
+
+
 @dataclasses.dataclass
 class Result:
     """Per-frame estimates (device tensors of length B)."""
@@ -75,11 +80,7 @@ class Result:
         return self.raw[:, 7]
 
     def numpy(self):
-        import numpy as np
-        dt = np.dtype([("cx", "<f4"), ("cy", "<f4"), ("r", "<f4"), ("score", "<f4"),
-                       ("inliers", "<i4"), ("n_points", "<i4"), ("valid", "<i4"),
-                       ("reason", "<i4")])
-        return self.raw.cpu().numpy().view(dt).reshape(-1)
+        return self.raw.cpu().numpy().view(RESULT_DTYPE).reshape(-1)
 
 
 _layout_cache: dict = {}

@@ -39,8 +39,26 @@ def test_learned_flops_per_frame():
 
 
 def test_ransac_flops_counts_frames_with_three_points():
+    # the method: one squared distance (5 flops) per attempt, point and pass
     assert bench.ransac_flops([0, 2], 1024, 3) == 0.0
-    assert bench.ransac_flops([100], 1024, 3) == 1024 * 100 * (3 * 23 + 9)
+    assert bench.ransac_flops([100], 1024, 3) == 1024 * 100 * 4 * 5
+    assert bench.ransac_flops([100, 7], 256, 0) == 256 * 107 * 5
+    # the kernel's issued FP64 operations, reported beside
+    assert bench.ransac_issued_flops([100], 1024, 3) == 1024 * 100 * (3 * 23 + 9)
+
+
+def test_graph_calls_cover_every_context_and_batch():
+    # 20 steps over 4 contexts and 5 batches: one call per graph
+    assert bench.graph_calls(20, 10, 20) == 1
+    assert bench.graph_calls(1000, 10, 20) == 10
+    assert bench.graph_calls(100, 10, 20) == 5
+    assert bench.graph_calls(7, 10, 20) == 1
+    for K in (1, 5, 20, 37, 100, 1000):
+        G = bench.graph_calls(K, 10, 20)
+        assert K % G == 0
+        assert K // G >= 20 or G == 1
+    assert bench.rotation_used(20, 4, 5) == {"contexts": 4, "batches": 5}
+    assert bench.rotation_used(2, 4, 5) == {"contexts": 2, "batches": 2}
 
 
 def _fake_tree(tmp_path, source: bytes, recorded_sha: str):

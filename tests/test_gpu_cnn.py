@@ -94,6 +94,73 @@ def test_learned_candidates_are_valid_argmax(torch_dev, est):
             assert abs(gs - sc[idx[0]]) <= tol
 
 
+def test_trained_scorer_1080p_candidates_ransac_and_fallback(torch_dev):
+    """The committed trained network on two headline 1080p frames with 32+32
+    strips: every candidate is a within-tolerance maximum of the numpy
+    statement's half-strip scores; the RANSAC over the kept learned
+    candidates equals the oracle's attempt by attempt; with the 0.5 inlier
+    fallback a frame below the fraction carries the oracle's handcrafted
+    result, any other frame the learned one."""
+    import os
+
+    import oracle
+    from paper_2210_14771_amd import train_scorer
+
+    from gpu_helpers import assert_attempts_equal, assert_results_equal, oracle_params
+
+    torch = torch_dev
+    path = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE)
+    if not os.path.exists(path):
+        pytest.skip("no trained scorer model")
+    flat = train_scorer.load_model(path)
+    params = [(cnn.bf16(w), b) for w, b in cnn.unflat_params(flat.astype(np.float64))]
+    e = api.Estimator(0)
+    e.set_model(flat)
+    frames, _ = synth.make_batch(synth.HD_1080p, 2)
+    dev = torch.from_numpy(frames).cuda()
+    uids = [0, 1]
+    kw = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+    say("trained scorer at 1080p: candidates")
+    _, pts = e.debug_candidates(dev, api.default_params(**kw, scorer=1), uids)
+    res_l, att = e.debug_attempts(dev, api.default_params(**kw, scorer=1), uids)
+    res_f = e.estimate_area(dev, api.default_params(**kw, scorer=1, fallback_inlier_frac=0.5),
+                            uids)
+    torch.cuda.synchronize()
+    g = api.points_numpy(pts)
+    res_l, res_f = res_l.numpy(), res_f.numpy()
+    att = api.attempts_numpy(att)
+    tol = 0.01
+    op = oracle_params(**kw)
+    for f in range(2):
+        halves = cnn.learned_half_strip_scores(frames[f], params, 32, 32)
+        assert len(halves) == 128
+        for c, (xs, ys, sc) in enumerate(halves):
+            gx, gy, gs = int(g[f][c]["x"]), int(g[f][c]["y"]), float(g[f][c]["score"])
+            idx = np.flatnonzero((xs == gx) & (ys == gy))
+            assert idx.size == 1, (f, c, gx, gy)
+            assert sc[idx[0]] >= sc.max() - tol, (f, c, sc[idx[0]], sc.max())
+            assert abs(gs - sc[idx[0]]) <= tol
+        # the learned form keeps points by score alone (no edge-distance filter)
+        s32 = g[f]["score"].astype(np.float32)
+        keep = s32 >= np.float32(op.t_ps)
+        xs = g[f]["x"][keep].astype(np.int32)
+        ys = g[f]["y"][keep].astype(np.int32)
+        sq = (s32[keep].astype(np.float64) * 2.0 ** 24).astype(np.uint32)
+        assert int(res_l[f]["n_points"]) == int(keep.sum())
+        say(f"frame {f}: {int(keep.sum())} learned points kept, oracle RANSAC over them")
+        ora_att = oracle.ransac_attempts(xs, ys, sq, 1920, 1080, uids[f], op)
+        assert_attempts_equal([att[f]], [ora_att])
+        n = int(res_l[f]["n_points"])
+        if n < 3 or np.float32(res_l[f]["inliers"]) < np.float32(0.5) * np.float32(n):
+            want = oracle.estimate(frames[f], op, uids[f]).copy()
+            want["reason"] += 256
+            say(f"frame {f}: fallback to the handcrafted pipeline")
+            assert_results_equal([res_f[f]], [want])
+        else:
+            assert res_f[f].tobytes() == res_l[f].tobytes()
+    e.close()
+
+
 # ----------------------------------------------------------------- training --
 #
 # The GPU backward pass stores its signals in bfloat16 and sums in float32;

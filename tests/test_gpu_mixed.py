@@ -1,13 +1,14 @@
 """Uneven batches: 512 frames of 720x576, 1280x720, 1920x1080 and 3840x2160
 in ratio 2:3:4:1 in one captured HIP graph, with autotuned strip tiles.
-Results must not depend on the tile (bit-exact against one strip item per
-workgroup), and sampled frames match the oracle one by one."""
+Every frame of the graph's output, under the split and the persistent
+schedule, matches the oracle (results exact, circles within 1e-3 px), and
+every frame's candidates match it bit for bit under each strip tile."""
 import numpy as np
 import pytest
 
 from paper_2210_14771_amd import api, synth
 
-from gpu_helpers import assert_points_equal, assert_results_equal, run_gpu, run_oracle, say
+from gpu_helpers import assert_points_equal, assert_results_equal, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -41,22 +42,37 @@ def batch(torch_dev):
     return frames, specs, views
 
 
+@pytest.fixture(scope="module")
+def oracle_out(batch):
+    frames, _, _ = batch
+    say(f"oracle on all {N} frames")
+    res, pts, _ = run_oracle(frames, KW, list(range(N)), threads=16)
+    return res, pts
+
+
 def _raw(res):
     import torch
     torch.cuda.synchronize()
     return res.raw.cpu().numpy()
 
 
-def test_graph_with_autotuned_tiles_equals_single_item_tiles(torch_dev, batch):
+def _as_results(raw):
+    return raw.view(api.RESULT_DTYPE).reshape(-1)
+
+
+def test_graph_with_autotuned_tiles_matches_oracle(torch_dev, batch, oracle_out):
     torch = torch_dev
     frames, specs, views = batch
+    ores, opts = oracle_out
     est = api.Estimator(0)
     params = api.default_params(**KW)
     uids = list(range(N))
     est.set_option("strips_per_group", 1)
     ref = _raw(est.estimate_area(views, params, uids))
+    assert_results_equal(_as_results(ref), ores)
     _, ref_pts = est.debug_candidates(views, params, uids)
     ref_pts = ref_pts.cpu().numpy()
+    assert_points_equal(api.points_numpy(torch.from_numpy(ref_pts)), opts)
     est.set_option("strips_per_group", 0)
     say("autotuning")
     tuned = est.autotune(views, params, uids, reps=3)
@@ -66,45 +82,25 @@ def test_graph_with_autotuned_tiles_equals_single_item_tiles(torch_dev, batch):
     assert set(tuned) == {(w, h) for w, h, _ in synth.MIXED_SHAPES}
     assert all(t in (1, 2, 4, 8) for t in tuned.values())
     out = torch.empty((N, 8), dtype=torch.int32, device="cuda")
-    g = est.capture(views, params, uids, out=out)
-    for rep in range(3):
-        out.zero_()
-        g.launch()
-        np.testing.assert_array_equal(_raw(api.Result(out)), ref, err_msg=f"replay {rep}")
-    g.close()
-    # the persistent schedule (one kernel drawing strip and RANSAC work
-    # items from per-XCD queues), captured the same way
-    est.set_option("schedule", "fused")
-    g = est.capture(views, params, uids, out=out)
-    for rep in range(2):
-        out.zero_()
-        g.launch()
-        np.testing.assert_array_equal(_raw(api.Result(out)), ref, err_msg=f"fused replay {rep}")
-    g.close()
+    # the split schedule with the tuned tiles (one strip launch per frame
+    # shape), then the persistent one (one kernel drawing strip and RANSAC
+    # work items from per-XCD queues), each captured as one graph
+    for sched in ("split", "fused"):
+        est.set_option("schedule", sched)
+        g = est.capture(views, params, uids, out=out)
+        for rep in range(2):
+            out.zero_()
+            g.launch()
+            got = _raw(api.Result(out))
+            say(f"{sched} replay {rep}: all {N} frames against the oracle")
+            assert_results_equal(_as_results(got), ores)
+            np.testing.assert_array_equal(got, ref, err_msg=f"{sched} replay {rep}")
+        g.close()
     est.device_status()        # raises if a wait hit its guard
     est.set_option("schedule", "split")
-    # every forced tile gives the same candidates
+    # every forced tile gives the oracle's candidates
     for t in (2, 8):
         est.set_option("strips_per_group", t)
         _, pts = est.debug_candidates(views, params, uids)
         np.testing.assert_array_equal(pts.cpu().numpy(), ref_pts, err_msg=f"tile {t}")
-    est.close()
-
-
-def test_sampled_frames_match_oracle(torch_dev, batch):
-    """Two frames of each resolution, from the 512-frame launch with tuned
-    tiles: candidates bit-exact, results exact (circles within 1e-3 px)."""
-    frames, specs, views = batch
-    est = api.Estimator(0)
-    uids = list(range(N))
-    est.autotune(views, api.default_params(**KW), uids, reps=1)
-    got = run_gpu(est, views, KW, uids, what=("pts",))
-    shapes = synth.mixed_shapes(N)
-    picks = []
-    for w, h, _ in synth.MIXED_SHAPES:
-        picks += [i for i in range(N) if shapes[i] == (w, h)][:2]
-    say(f"oracle on frames {picks}")
-    ores, opts, _ = run_oracle([frames[i] for i in picks], KW, picks, threads=8)
-    assert_points_equal([got["pts"][i] for i in picks], opts)
-    assert_results_equal([got["res"][i] for i in picks], ores)
     est.close()

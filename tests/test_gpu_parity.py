@@ -25,11 +25,16 @@ def torch_dev():
     return torch
 
 
-@pytest.fixture(scope="module", params=["split", "split_pipe1", "fused"])
+# split: one strip launch and one RANSAC launch per call; split_pipeN: the
+# call cut into N sub-batches alternating over two side streams forked from
+# and joined back into the caller's stream; fused: the persistent kernel
+@pytest.fixture(scope="module", params=["split", "split_pipe2", "split_pipe4", "fused"])
 def est(torch_dev, request):
     e = api.Estimator(0)
     e.set_option("schedule", "fused" if request.param == "fused" else "split")
-    if request.param == "split_pipe1":
+    if request.param.startswith("split_pipe"):
+        e.set_option("pipeline", int(request.param[len("split_pipe"):]))
+    else:
         e.set_option("pipeline", 1)
     say(f"schedule: {request.param}")
     yield e

@@ -1,6 +1,6 @@
 """The serving loop: continuous batching of simulated video streams.  Every
-frame's result equals the batch API's result for the same frame and uid,
-whether the stream is served alone or among 47 others; the per-stream
+frame's result equals the batch API's and the oracle's result for the same
+frame and uid, whether the stream is served alone or among 47 others; the per-stream
 temporal filter follows its definition; streams wait for memory and are
 admitted as others close."""
 import json
@@ -74,12 +74,21 @@ def test_results_identical_alone_and_in_the_mix(torch_dev, streams):
     est.close()
 
 
-def test_each_result_equals_the_batch_api(torch_dev, streams):
+def test_each_result_equals_the_batch_api_and_the_oracle(torch_dev, streams):
+    """Every served frame: the batch API's result for the same frame and uid,
+    and the oracle's (counts exact, circle within 1e-3 px)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    from gpu_helpers import assert_results_equal, oracle_params
+
     torch = torch_dev
     est = api.Estimator(0)
     srv = serve.Server(est, serve.server_config(max_batch=32, **KW))
     got, _ = serve.run(srv, streams[:6], realtime=False)
     srv.close()
+    host = {}
     for r in got:
         st = streams[r["stream"]]
         frame = st.frames[r["seq"] % len(st.frames)]
@@ -89,7 +98,18 @@ def test_each_result_equals_the_batch_api(torch_dev, streams):
         raw = res.raw.cpu().numpy()[0]
         want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
         assert r["result"] == want, (r["stream"], r["seq"])
+        host[_key(r)] = (frame.cpu().numpy(), uid)
     est.close()
+    op = oracle_params(**KW)
+    keys = sorted(host)
+    say(f"oracle on {len(keys)} served frames")
+    with ThreadPoolExecutor(16) as ex:
+        ora = list(ex.map(lambda k: oracle.estimate(host[k][0], op, host[k][1]), keys))
+    by = {_key(r): r for r in got}
+    gpu = np.zeros(len(keys), dtype=api.RESULT_DTYPE)
+    for i, k in enumerate(keys):
+        gpu[i] = by[k]["result"]
+    assert_results_equal(gpu, ora)
 
 
 def test_temporal_filter_follows_its_definition(torch_dev, streams):
