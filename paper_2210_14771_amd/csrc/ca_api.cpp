@@ -118,12 +118,32 @@ int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p)
     return CA_OK;
 }
 
-int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out)
+const float *cached_tables(ca_ctx *ctx, const ca_params &p, int32_t *sg_len)
 {
-    Plan *pl = new (std::nothrow) Plan();
-    if (!pl)
-        return CA_E_NOMEM;
-    pl->dims.assign(dims, dims + n);
+    // the score tables of the last (t_g, t_theta, t_iota) are kept in the
+    // context: SG[sg_len] | ST[2049] | SI[256]
+    if (!ctx->lut_valid || ctx->lut_key[0] != p.t_g || ctx->lut_key[1] != p.t_theta_deg
+        || ctx->lut_key[2] != p.t_iota) {
+        float *sg = ctx->lut_cache;
+        int32_t n = 0;
+        score_tables(p, sg, &n, ctx->lut_st, ctx->lut_si);
+        std::memmove(sg + n, ctx->lut_st, sizeof(float) * ca::kQtBins);
+        std::memmove(sg + n + ca::kQtBins, ctx->lut_si, sizeof(float) * ca::kLumaLevels);
+        ctx->lut_sg_len = n;
+        ctx->lut_key[0] = p.t_g;
+        ctx->lut_key[1] = p.t_theta_deg;
+        ctx->lut_key[2] = p.t_iota;
+        ctx->lut_valid = true;
+    }
+    *sg_len = ctx->lut_sg_len;
+    return ctx->lut_cache;
+}
+
+int plan_layout(const ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p,
+                const float *lut, int32_t sg_len, Shape *shapes, int32_t max_shapes, Plan *pl,
+                PlanLayout *L, uint8_t *image, size_t image_cap)
+{
+    const int32_t S = p.n_hstrips + p.n_vstrips;
     pl->n_frames = n;
     pl->n_h = p.n_hstrips;
     pl->n_v = p.n_vstrips;
@@ -132,81 +152,126 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
     pl->t_g = p.t_g;
     pl->t_theta = p.t_theta_deg;
     pl->t_iota = p.t_iota;
-    pl->P = 2 * (p.n_hstrips + p.n_vstrips);
+    pl->P = 2 * S;
     pl->groups = (p.ransac_attempts + ca::kAttemptsPerGroup - 1) / ca::kAttemptsPerGroup;
-
-    // host images of the tables
-    const int S = p.n_hstrips + p.n_vstrips;
-    std::vector<Shape> shapes;
-    std::vector<int32_t> strips;
-    std::vector<FrameDev> fd((size_t)n);
-    int32_t longest = 0;
+    pl->sg_len = sg_len;
+    // distinct frame shapes in order of first appearance
+    int32_t n_shapes = 0, longest = 0;
     pl->rows_aligned = true;
     for (int32_t i = 0; i < n; ++i) {
         const ca_frame_desc &d = dims[i];
-        size_t k = 0;
-        while (k < shapes.size() && !(shapes[k].W == d.width && shapes[k].H == d.height))
+        int32_t k = 0;
+        while (k < n_shapes && !(shapes[k].W == d.width && shapes[k].H == d.height))
             ++k;
-        if (k == shapes.size()) {
-            shapes.push_back({d.width, d.height});
-            const size_t at = strips.size();
-            strips.resize(at + (size_t)S);
-            strip_positions(d.height, p.n_hstrips, p.alpha, strips.data() + at);
-            strip_positions(d.width, p.n_vstrips, p.alpha, strips.data() + at + p.n_hstrips);
+        if (k == n_shapes) {
+            if (n_shapes == max_shapes)
+                return CA_E_NOMEM;
+            shapes[n_shapes++] = {d.width, d.height};
         }
-        fd[(size_t)i] = FrameDev{d.byte_offset, d.width, d.height, d.row_stride,
-                                 (int32_t)(k * (size_t)S), d.frame_uid};
-        longest = d.width > longest ? d.width : longest;
-        longest = d.height > longest ? d.height : longest;
+        longest = std::max(longest, std::max(d.width, d.height));
         if ((d.byte_offset % 16) != 0 || (d.row_stride % 16) != 0)
             pl->rows_aligned = false;
     }
-    // frames grouped by shape: the strip kernel is launched per shape class
-    std::vector<int32_t> flist;
-    flist.reserve((size_t)n);
-    for (size_t k = 0; k < shapes.size(); ++k) {
-        const int32_t first = (int32_t)flist.size();
-        for (int32_t i = 0; i < n; ++i)
-            if (dims[i].width == shapes[k].W && dims[i].height == shapes[k].H)
-                flist.push_back(i);
-        pl->classes.push_back({shapes[k].W, shapes[k].H, first, (int32_t)flist.size() - first});
-    }
-    pl->shapes = shapes;
-    std::vector<float> lut((size_t)CA_SG_CAPACITY + ca::kQtBins + ca::kLumaLevels);
-    int32_t sg_len = 0;
-    std::vector<float> st(ca::kQtBins), si(ca::kLumaLevels);
-    score_tables(p, lut.data(), &sg_len, st.data(), si.data());
-    std::memcpy(lut.data() + sg_len, st.data(), sizeof(float) * ca::kQtBins);
-    std::memcpy(lut.data() + sg_len + ca::kQtBins, si.data(), sizeof(float) * ca::kLumaLevels);
-    lut.resize((size_t)sg_len + ca::kQtBins + ca::kLumaLevels);
-    pl->sg_len = sg_len;
     pl->line_pitch = (int32_t)align_up((size_t)longest, 16);
     pl->lds = ca::strip_lds_bytes(sg_len, pl->line_pitch);
     pl->fused_lds = ca::fused_lds_bytes(sg_len, pl->line_pitch);
-    if (pl->lds > ctx->max_lds || pl->fused_lds > ctx->max_lds) {
-        delete pl;
+    if (pl->lds > ctx->max_lds || pl->fused_lds > ctx->max_lds)
         return CA_E_UNSUPPORTED;
+    const size_t lut_len = (size_t)sg_len + ca::kQtBins + ca::kLumaLevels;
+    L->n_shapes = n_shapes;
+    L->o_fd = 0;
+    L->o_strips = align_up(sizeof(FrameDev) * (size_t)n, 256);
+    L->o_lut = align_up(L->o_strips + sizeof(int32_t) * (size_t)n_shapes * (size_t)S, 256);
+    L->o_flist = align_up(L->o_lut + sizeof(float) * lut_len, 256);
+    L->o_ctl = align_up(L->o_flist + sizeof(int32_t) * (size_t)n, 256);
+    L->image_bytes = L->o_ctl + sizeof(uint32_t) * ca::ctl_words(n);
+    L->o_cand = align_up(L->image_bytes, 256);
+    L->o_rec = align_up(L->o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
+    L->o_res2 = align_up(L->o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
+    L->total = align_up(L->o_res2 + sizeof(ca_result) * (size_t)n, 256);
+    if (!image)
+        return CA_OK;
+    if (image_cap < L->image_bytes)
+        return CA_E_NOMEM;
+    std::memset(image, 0, L->image_bytes);
+    FrameDev *fd = reinterpret_cast<FrameDev *>(image + L->o_fd);
+    int32_t *strips = reinterpret_cast<int32_t *>(image + L->o_strips);
+    int32_t *flist = reinterpret_cast<int32_t *>(image + L->o_flist);
+    for (int32_t k = 0; k < n_shapes; ++k) {
+        strip_positions(shapes[k].H, p.n_hstrips, p.alpha, strips + (size_t)k * S);
+        strip_positions(shapes[k].W, p.n_vstrips, p.alpha, strips + (size_t)k * S + p.n_hstrips);
     }
+    std::memcpy(image + L->o_lut, lut, sizeof(float) * lut_len);
+    // frame indices grouped by shape: the strip kernel may be launched per shape
+    int32_t at = 0;
+    for (int32_t k = 0; k < n_shapes; ++k)
+        for (int32_t i = 0; i < n; ++i)
+            if (dims[i].width == shapes[k].W && dims[i].height == shapes[k].H) {
+                flist[at++] = i;
+                const ca_frame_desc &d = dims[i];
+                fd[i] = FrameDev{d.byte_offset, d.width, d.height, d.row_stride, k * S, d.frame_uid};
+            }
+    return CA_OK;
+}
+
+void plan_pointers(Plan *pl, void *base_mem, const PlanLayout &L)
+{
+    uint8_t *base = static_cast<uint8_t *>(base_mem);
+    pl->fd = reinterpret_cast<FrameDev *>(base + L.o_fd);
+    pl->strips = reinterpret_cast<int32_t *>(base + L.o_strips);
+    pl->lut = reinterpret_cast<float *>(base + L.o_lut);
+    pl->flist = reinterpret_cast<int32_t *>(base + L.o_flist);
+    pl->ctl = reinterpret_cast<uint32_t *>(base + L.o_ctl);
+    pl->cand = reinterpret_cast<ca_point *>(base + L.o_cand);
+    pl->rec = reinterpret_cast<Record *>(base + L.o_rec);
+    pl->res2 = reinterpret_cast<ca_result *>(base + L.o_res2);
+}
+
+int fused_grid(const ca_ctx *ctx, size_t fused_lds)
+{
     int per_cu = 0;
-    if (ca::fused_occupancy(pl->fused_lds, &per_cu) != hipSuccess || per_cu < 1) {
+    if (ca::fused_occupancy(fused_lds, &per_cu) != hipSuccess || per_cu < 1) {
         (void)hipGetLastError();
         per_cu = 1;
     }
-    pl->fused_grid = per_cu * ctx->n_cu;
+    return per_cu * ctx->n_cu;
+}
 
-    // one device allocation: frames | strips | lut | candidates | records
-    const size_t o_fd = 0;
-    const size_t o_strips = align_up(o_fd + sizeof(FrameDev) * (size_t)n, 256);
-    const size_t o_lut = align_up(o_strips + sizeof(int32_t) * strips.size(), 256);
-    const size_t o_cand = align_up(o_lut + sizeof(float) * lut.size(), 256);
-    const size_t o_rec = align_up(o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
-    const size_t o_ctl = align_up(o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
-    const size_t o_res2 = align_up(o_ctl + sizeof(uint32_t) * ca::ctl_words(n), 256);
-    const size_t o_flist = align_up(o_res2 + sizeof(ca_result) * (size_t)n, 256);
-    const size_t total = align_up(o_flist + sizeof(int32_t) * (size_t)n, 256);
+int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out)
+{
+    Plan *pl = new (std::nothrow) Plan();
+    if (!pl)
+        return CA_E_NOMEM;
+    pl->dims.assign(dims, dims + n);
+    int32_t sg_len = 0;
+    const float *lut = cached_tables(ctx, p, &sg_len);
+    std::vector<Shape> shapes((size_t)n);
+    PlanLayout L;
+    int rc = plan_layout(ctx, dims, n, p, lut, sg_len, shapes.data(), n, pl, &L, nullptr, 0);
+    std::vector<uint8_t> image;
+    if (rc == CA_OK) {
+        image.resize(L.image_bytes);
+        rc = plan_layout(ctx, dims, n, p, lut, sg_len, shapes.data(), n, pl, &L, image.data(),
+                         image.size());
+    }
+    if (rc != CA_OK) {
+        delete pl;
+        return rc;
+    }
+    shapes.resize((size_t)L.n_shapes);
+    int32_t first = 0;
+    for (const Shape &sh : shapes) {
+        int32_t count = 0;
+        for (int32_t i = 0; i < n; ++i)
+            count += dims[i].width == sh.W && dims[i].height == sh.H;
+        pl->classes.push_back({sh.W, sh.H, first, count});
+        first += count;
+    }
+    pl->shapes = shapes;
+    pl->fused_grid = fused_grid(ctx, pl->fused_lds);
 
     // evict least recently used unpinned plans until this one fits the budget
-    while (ctx->used + total > ctx->budget) {
+    while (ctx->used + L.total > ctx->budget) {
         long lru = -1;
         for (size_t k = 0; k < ctx->plans.size(); ++k)
             if (ctx->plans[k]->pins == 0
@@ -217,39 +282,21 @@ int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_param
         free_plan(ctx, ctx->plans[(size_t)lru]);
         ctx->plans.erase(ctx->plans.begin() + lru);
     }
-    if (ctx->used + total > ctx->budget) {
+    if (ctx->used + L.total > ctx->budget) {
         delete pl;
         return CA_E_NOMEM;
     }
-    if (hipMalloc(&pl->mem, total) != hipSuccess) {
+    if (hipMalloc(&pl->mem, L.total) != hipSuccess) {
         (void)hipGetLastError();
         delete pl;
         return CA_E_NOMEM;
     }
-    pl->bytes = total;
-    ctx->used += total;
-    uint8_t *base = static_cast<uint8_t *>(pl->mem);
-    pl->fd = reinterpret_cast<FrameDev *>(base + o_fd);
-    pl->strips = reinterpret_cast<int32_t *>(base + o_strips);
-    pl->lut = reinterpret_cast<float *>(base + o_lut);
-    pl->cand = reinterpret_cast<ca_point *>(base + o_cand);
-    pl->rec = reinterpret_cast<Record *>(base + o_rec);
-    pl->ctl = reinterpret_cast<uint32_t *>(base + o_ctl);
-    pl->res2 = reinterpret_cast<ca_result *>(base + o_res2);
-    pl->flist = reinterpret_cast<int32_t *>(base + o_flist);
+    pl->bytes = L.total;
+    ctx->used += L.total;
+    plan_pointers(pl, pl->mem, L);
     // plans are built once per batch shape; a blocking upload keeps them simple
-    bool ok = hipMemcpy(pl->fd, fd.data(), sizeof(FrameDev) * (size_t)n, hipMemcpyHostToDevice)
-                  == hipSuccess
-              && hipMemcpy(pl->strips, strips.data(), sizeof(int32_t) * strips.size(),
-                           hipMemcpyHostToDevice)
-                     == hipSuccess
-              && hipMemcpy(pl->lut, lut.data(), sizeof(float) * lut.size(), hipMemcpyHostToDevice)
-                     == hipSuccess
-              && hipMemcpy(pl->flist, flist.data(), sizeof(int32_t) * flist.size(),
-                           hipMemcpyHostToDevice) == hipSuccess
-              && hipMemset(pl->ctl, 0, sizeof(uint32_t) * ca::ctl_words(n)) == hipSuccess
-              && hipDeviceSynchronize() == hipSuccess;
-    if (!ok) {
+    if (hipMemcpy(pl->mem, image.data(), image.size(), hipMemcpyHostToDevice) != hipSuccess
+        || hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         free_plan(ctx, pl);
         return CA_E_DEVICE;

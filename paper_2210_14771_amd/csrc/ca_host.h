@@ -103,12 +103,44 @@ struct ca_ctx {
     int64_t strips_per_group = 0;   // 0: tuned per frame shape
     int cnn_groups_per_xcd = 0;     // resident learned-strip workgroups per XCD (0: not queried)
     std::map<std::array<int32_t, 4>, int32_t> tuned;   // (W, H, n_h, n_v) -> strip items per group
+    // score tables of the last (t_g, t_theta, t_iota): SG[lut_sg_len] | ST | SI
+    bool lut_valid = false;
+    double lut_key[3] = {0, 0, 0};
+    int32_t lut_sg_len = 0;
+    float lut_cache[CA_SG_CAPACITY + ca::kQtBins + ca::kLumaLevels];
+    float lut_st[ca::kQtBins];
+    float lut_si[ca::kLumaLevels];
 };
 
 
 namespace cahost {
 
 int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p);
+
+// Byte layout of a plan's device block.  Its first image_bytes bytes
+// (frame descriptors, strip tables, score tables, frame list grouped by
+// shape, zeroed control words) are built on the host and uploaded with one
+// copy; candidates, attempt-group records and fallback results follow and
+// are written by the kernels only.
+struct PlanLayout {
+    size_t o_fd = 0, o_strips = 0, o_lut = 0, o_flist = 0, o_ctl = 0, image_bytes = 0;
+    size_t o_cand = 0, o_rec = 0, o_res2 = 0, total = 0;
+    int32_t n_shapes = 0;
+};
+// The context's score tables for p (computed once per (t_g, t_theta, t_iota)).
+const float *cached_tables(ca_ctx *ctx, const ca_params &p, int32_t *sg_len);
+// Launch facts of pl (P, groups, sg_len, line pitch, LDS sizes, row
+// alignment; not the fused grid) and the layout L; the distinct shapes go to
+// shapes[0 .. max_shapes).  With `image`, also writes the host image
+// (image_cap >= L->image_bytes).  CA_E_NOMEM for more than max_shapes
+// shapes or a short image, CA_E_UNSUPPORTED when a strip tile exceeds LDS.
+int plan_layout(const ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p,
+                const float *lut, int32_t sg_len, Shape *shapes, int32_t max_shapes, Plan *pl,
+                PlanLayout *L, uint8_t *image, size_t image_cap);
+// Points pl's buffers into the device block at base.
+void plan_pointers(Plan *pl, void *base, const PlanLayout &L);
+// Resident workgroups of the fused kernel for this LDS size.
+int fused_grid(const ca_ctx *ctx, size_t fused_lds);
 int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out);
 void free_plan(ca_ctx *ctx, Plan *pl);
 // Enqueue the whole path for frames [0, n) of a plan on stream s.
