@@ -63,6 +63,9 @@ def parse():
                     help="timed graph replays of the 512-frame uneven batch (0: skip)")
     ap.add_argument("--small-steps", type=int, default=20,
                     help="timed graph launches (100 calls each) of the 8 x 640x480 case (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=0.4,
+                    help="seconds of simulated arrivals of the 48-stream serving loop, plain "
+                         "and learned side by side, in a child process (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -346,6 +349,26 @@ def mixed_section(args, est, kw):
             "frame_bytes": int(sum(sizes))}
 
 
+def serving_section(args):
+    """The serving loop (48 streams of 720p, 1080p and 4K, Poisson arrivals at
+    30-60 frames/s each, continuous batching): p50/p99 latency and frames/s
+    with the plain and the learned scorer, from serve_bench in a child
+    process with a time limit of its own."""
+    import subprocess
+    if args.serve_seconds <= 0:
+        return None
+    cmd = [sys.executable, "-m", "paper_2210_14771_amd.serve_bench", "--seconds",
+           str(args.serve_seconds)]
+    try:
+        r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=180)
+    except subprocess.TimeoutExpired:
+        return {"status": "timeout", "limit_s": 180}
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"status": "failed", "rc": r.returncode, "stderr": r.stderr[-400:]}
+    return json.loads(lines[-1])
+
+
 def run_environment(params) -> dict:
     import torch
     try:
@@ -369,7 +392,7 @@ def cpu_baseline(frames, kw, target_cpu_s: float, threads: int | None = None):
     t0 = time.perf_counter()
     oracle.estimate_batch(sample, p, threads=threads)
     t1 = time.perf_counter() - t0
-    reps = max(1, min(50, math.ceil(target_cpu_s / max(t1 * threads, 1e-6))))
+    reps = max(1, min(1000, math.ceil(target_cpu_s / max(t1 * threads, 1e-6))))
     t0 = time.perf_counter()
     for _ in range(reps):
         oracle.estimate_batch(sample, p, threads=threads)
@@ -650,6 +673,10 @@ def main():
     small = small_section(args)
     if small is not None:
         line["small_640x480"] = small
+    print("# serving", file=sys.stderr, flush=True)
+    serving = serving_section(args)
+    if serving is not None:
+        line["serving"] = serving
     line["env"] = run_environment(params)
     line["hbm_copy_gbps"] = copy_bandwidth(dev)
     if not args.no_cpu_baseline:

@@ -408,8 +408,11 @@ typedef struct {
 } ca_served;
 
 /* Create a server on a context with a learned model if params.scorer asks
- * for it (ca_set_model first).  Allocates the budget, per-batch buffers and
- * one HIP stream (default priority) on which all of its work runs in order.
+ * for it (ca_set_model first).  Allocates (blocking) everything the server
+ * will use: the budget, per in-flight batch one device block sized for
+ * max_batch frames (descriptors, one strip table per frame, score tables,
+ * candidates, attempt records) with its pinned staging, and one HIP stream
+ * (default priority) on which all of its work runs in order.
  * CA_E_INVAL for a bad config, CA_E_NOMEM. */
 int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **server);
 
@@ -418,10 +421,10 @@ void ca_server_destroy(ca_server *server);
 
 /* Open stream `stream_id` (>= 0, not open) with frames of width x height
  * (16 .. CA_MAX_EXTENT each).  *admitted = 1 if its ring was reserved now,
- * 0 if it waits for memory.  The first stream of a new frame shape makes the
- * next launches rebuild the server's strip tables (a blocking step).
- * CA_E_INVAL for a bad shape, a negative or duplicate id, or a ring larger
- * than the whole budget. */
+ * 0 if it waits for memory.  The stream's strip positions (Eq. 1) are
+ * computed here; each batch then carries the tables of its own shapes, so
+ * any number of distinct shapes may be open.  CA_E_INVAL for a bad shape, a
+ * negative or duplicate id, or a ring larger than the whole budget. */
 int ca_server_open(ca_server *server, int32_t stream_id, int32_t width, int32_t height,
                    int32_t *admitted);
 
@@ -436,9 +439,12 @@ int ca_server_close(ca_server *server, int32_t stream_id);
 int ca_server_submit(ca_server *server, int32_t stream_id, uint64_t seq, const uint8_t *src,
                      int64_t row_stride, int32_t src_is_device);
 
-/* Make progress (never blocks on the GPU); write up to max_out served frames
- * to `out` (host) in completion order, their count to *n_out.  Served frames
- * beyond max_out are kept for the next call. */
+/* Make progress; write up to max_out served frames to `out` (host) in
+ * completion order, their count to *n_out.  Served frames beyond max_out are
+ * kept for the next call.  Never blocks on the GPU: the call only polls
+ * events and enqueues asynchronous copies (into ring slots, and from and to
+ * pinned staging) and kernels on the server's stream; it allocates,
+ * frees and synchronises nothing. */
 int ca_server_step(ca_server *server, ca_served *out, int32_t max_out, int32_t *n_out);
 
 /* Counts: [0] frames submitted, [1] served, [2] queued on the host,

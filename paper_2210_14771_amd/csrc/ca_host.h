@@ -116,6 +116,8 @@ struct ca_ctx {
 namespace cahost {
 
 int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p);
+// Eq. 1 positions of n strips across an extent (floor, clamped to [1, extent - 2]).
+int strip_positions(int32_t extent, int32_t n, double alpha, int32_t *pos);
 
 // Byte layout of a plan's device block.  Its first image_bytes bytes
 // (frame descriptors, strip tables, score tables, frame list grouped by

@@ -8,6 +8,15 @@
 // work waits on another stream.  Device side: the
 // estimator's kernels on each batch, then one kernel that folds the batch's
 // results into the per-stream filtered circles, in sequence order.
+//
+// Every buffer is allocated, and every table computed, in ca_server_create
+// (per in-flight slot: one block of max_batch frames' descriptors, strip
+// tables, score tables, candidates and records, plus pinned staging) and in
+// ca_server_open (the stream's strip positions).  ca_server_step only
+// queries events and enqueues asynchronous work: event queries, copies into
+// ring slots, one copy of the batch's descriptors and strip tables from
+// pinned staging, the kernels, copies of the results into pinned memory, an
+// event record.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -97,6 +106,7 @@ struct Stream {
     int64_t outstanding = 0;             // copied or in flight, not yet served
     uint64_t last_seq = 0;
     bool any_seq = false;
+    std::vector<int32_t> table;          // strip positions: n_h rows then n_v columns
 };
 
 struct Entry {                          // one frame from copy to retirement
@@ -107,12 +117,11 @@ struct Entry {                          // one frame from copy to retirement
 };
 
 struct Batch {                          // one in-flight slot
-    cahost::Plan *plan = nullptr;
-    uint64_t plan_version = 0;
+    cahost::Plan plan;                  // buffers for max_batch frames, one device block
     ca_result *res_dev = nullptr;       // [max_batch]
     float4 *filt_dev = nullptr;         // [max_batch]
     int4 *runs_dev = nullptr;           // [max_batch]
-    ca::FrameDev *fd_host = nullptr;    // pinned staging
+    uint8_t *stage = nullptr;           // pinned: descriptors, then strip tables
     int4 *runs_host = nullptr;
     ca_result *res_host = nullptr;
     float4 *filt_host = nullptr;
@@ -139,8 +148,8 @@ struct ca_server {
     std::vector<Batch> batches;
     std::deque<size_t> inflight;        // batch slots in launch order
     std::deque<ca_served> done;         // served, not yet returned
-    std::vector<cahost::Shape> shapes;  // every frame shape opened so far
-    uint64_t shapes_version = 0;
+    cahost::PlanLayout layout;          // of every slot's block (max_batch frames)
+    std::map<int32_t, int32_t> fused_grid;  // per LDS line pitch (fused schedule only)
     int64_t n_submitted = 0, n_served = 0, n_batches = 0;
 };
 
@@ -151,55 +160,65 @@ size_t frame_bytes(int32_t W, int32_t H)
     return ((size_t)3 * W * H + kSlotAlign - 1) / kSlotAlign * kSlotAlign;
 }
 
-int32_t shape_index(const std::vector<cahost::Shape> &shapes, int32_t W, int32_t H)
-{
-    for (size_t k = 0; k < shapes.size(); ++k)
-        if (shapes[k].W == W && shapes[k].H == H)
-            return (int32_t)k;
-    return -1;
-}
-
-// A serving plan holding strip tables for every shape opened so far.
-int rebuild_plan(ca_server *s, Batch &b)
-{
-    if (b.plan) {
-        cahost::free_plan(s->ctx, b.plan);
-        s->ctx->plans.erase(std::find(s->ctx->plans.begin(), s->ctx->plans.end(), b.plan));
-        b.plan = nullptr;
-    }
-    const int32_t n = s->cfg.max_batch;
-    std::vector<ca_frame_desc> dims((size_t)n);
-    for (int32_t i = 0; i < n; ++i) {
-        const cahost::Shape &sh = s->shapes[std::min<size_t>((size_t)i, s->shapes.size() - 1)];
-        ca_frame_desc &d = dims[(size_t)i];
-        std::memset(&d, 0, sizeof(d));
-        d.width = sh.W;
-        d.height = sh.H;
-        d.row_stride = 3 * sh.W;
-        d.pixel_stride = 3;
-    }
-    cahost::Plan *pl = nullptr;
-    const int rc = cahost::build_plan(s->ctx, dims.data(), n, s->cfg.params, &pl);
-    if (rc != CA_OK)
-        return rc;
-    pl->dynamic = true;
-    pl->pins = 1;
-    b.plan = pl;
-    b.plan_version = s->shapes_version;
-    return CA_OK;
-}
-
 void free_batch(Batch &b)
 {
     if (b.done)
         (void)hipEventDestroy(b.done);
+    (void)hipFree(b.plan.mem);
     (void)hipFree(b.res_dev);
     (void)hipFree(b.filt_dev);
     (void)hipFree(b.runs_dev);
-    (void)hipHostFree(b.fd_host);
+    (void)hipHostFree(b.stage);
     (void)hipHostFree(b.runs_host);
     (void)hipHostFree(b.res_host);
     (void)hipHostFree(b.filt_host);
+}
+
+// The launch facts of a batch: its frames' descriptors and the strip tables
+// of its distinct shapes into the slot's pinned staging (laid out as the
+// head of the device block), the LDS line pitch of its longest extent.
+// Returns the bytes to upload.
+size_t stage_batch(ca_server *s, Batch &b, size_t n)
+{
+    const int32_t S = s->cfg.params.n_hstrips + s->cfg.params.n_vstrips;
+    ca::FrameDev *fd = reinterpret_cast<ca::FrameDev *>(b.stage + s->layout.o_fd);
+    int32_t *tables = reinterpret_cast<int32_t *>(b.stage + s->layout.o_strips);
+    std::vector<const Stream *> shapes;  // one strip table per distinct shape
+    int32_t longest = 0;
+    bool aligned = true;
+    for (size_t i = 0; i < n; ++i) {
+        const Entry &e = b.entries[i];
+        size_t k = 0;
+        while (k < shapes.size() && !(shapes[k]->W == e.st->W && shapes[k]->H == e.st->H))
+            ++k;
+        if (k == shapes.size()) {
+            shapes.push_back(e.st);
+            std::memcpy(tables + k * (size_t)S, e.st->table.data(), sizeof(int32_t) * (size_t)S);
+        }
+        ca::FrameDev &d = fd[i];
+        d.offset = (int64_t)(e.st->ring_off + (size_t)e.slot * e.st->slot_bytes);
+        d.W = e.st->W;
+        d.H = e.st->H;
+        d.rs = 3 * e.st->W;
+        d.table = (int32_t)k * S;
+        d.uid = ((uint64_t)(uint32_t)e.st->id << 32) | (e.seq & 0xFFFFFFFFull);
+        longest = std::max(longest, std::max(e.st->W, e.st->H));
+        aligned = aligned && (d.rs % 16) == 0;     // ring slots start 256-byte aligned
+    }
+    cahost::Plan &pl = b.plan;
+    pl.n_frames = (int32_t)n;
+    pl.line_pitch = (int32_t)cahost::align_up((size_t)longest, 16);
+    pl.lds = ca::strip_lds_bytes(pl.sg_len, pl.line_pitch);
+    pl.fused_lds = ca::fused_lds_bytes(pl.sg_len, pl.line_pitch);
+    pl.rows_aligned = aligned;
+    if (s->ctx->schedule == CA_SCHEDULE_FUSED) {
+        auto it = s->fused_grid.find(pl.line_pitch);
+        if (it == s->fused_grid.end())
+            it = s->fused_grid.emplace(pl.line_pitch, cahost::fused_grid(s->ctx, pl.fused_lds))
+                     .first;
+        pl.fused_grid = it->second;
+    }
+    return s->layout.o_strips + sizeof(int32_t) * shapes.size() * (size_t)S;
 }
 
 bool try_admit(ca_server *s, Stream *st)
@@ -320,11 +339,6 @@ int launch(ca_server *s)
         if (slot == s->batches.size())
             return CA_OK;
         Batch &b = s->batches[slot];
-        if (!b.plan || b.plan_version != s->shapes_version) {
-            const int rc = rebuild_plan(s, b);
-            if (rc != CA_OK)
-                return rc;
-        }
         const size_t n = std::min<size_t>(s->ready.size(), (size_t)s->cfg.max_batch);
         b.entries.assign(s->ready.begin(), s->ready.begin() + (ptrdiff_t)n);
         s->ready.erase(s->ready.begin(), s->ready.begin() + (ptrdiff_t)n);
@@ -332,30 +346,22 @@ int launch(ca_server *s)
         std::stable_sort(b.entries.begin(), b.entries.end(), [](const Entry &x, const Entry &y) {
             return x.st->state != y.st->state ? x.st->state < y.st->state : x.seq < y.seq;
         });
-        const int32_t S = s->cfg.params.n_hstrips + s->cfg.params.n_vstrips;
         int32_t n_runs = 0;
         for (size_t i = 0; i < n; ++i) {
             const Entry &e = b.entries[i];
-            ca::FrameDev &d = b.fd_host[i];
-            d.offset = (int64_t)(e.st->ring_off + (size_t)e.slot * e.st->slot_bytes);
-            d.W = e.st->W;
-            d.H = e.st->H;
-            d.rs = 3 * e.st->W;
-            d.table = shape_index(b.plan->shapes, e.st->W, e.st->H) * S;
-            d.uid = ((uint64_t)(uint32_t)e.st->id << 32) | (e.seq & 0xFFFFFFFFull);
             if (i == 0 || b.entries[i - 1].st != e.st)
                 b.runs_host[n_runs++] = make_int4(e.st->state, (int)i, (int)i + 1, 0);
             else
                 b.runs_host[n_runs - 1].z = (int)i + 1;
         }
+        const size_t upload = stage_batch(s, b, n);
         // the batch's frames were copied earlier on the same stream
         const hipStream_t cs = s->compute;
-        if (hipMemcpyAsync(b.plan->fd, b.fd_host, n * sizeof(ca::FrameDev), hipMemcpyHostToDevice,
-                           cs) != hipSuccess
+        if (hipMemcpyAsync(b.plan.mem, b.stage, upload, hipMemcpyHostToDevice, cs) != hipSuccess
             || hipMemcpyAsync(b.runs_dev, b.runs_host, (size_t)n_runs * sizeof(int4),
                               hipMemcpyHostToDevice, cs) != hipSuccess)
             return CA_E_DEVICE;
-        int rc = cahost::enqueue(s->ctx, b.plan, s->arena_mem, (int32_t)n, s->cfg.params, nullptr,
+        int rc = cahost::enqueue(s->ctx, &b.plan, s->arena_mem, (int32_t)n, s->cfg.params, nullptr,
                                  nullptr, b.res_dev, cs, false);
         if (rc != CA_OK)
             return rc;
@@ -413,17 +419,58 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
               && hipMalloc(&s->state_dev, sizeof(float4) * (size_t)cfg->max_streams) == hipSuccess
               && hipMemset(s->state_dev, 0, sizeof(float4) * (size_t)cfg->max_streams)
                      == hipSuccess;
+    // the layout of a slot's block: max_batch frames, each of its own shape
+    // (so the strip tables of any batch fit), score tables uploaded once
+    int32_t sg_len = 0;
+    const float *lut = ok ? cahost::cached_tables(ctx, cfg->params, &sg_len) : nullptr;
+    std::vector<ca_frame_desc> dims(B);
+    for (size_t i = 0; i < B; ++i) {
+        ca_frame_desc &d = dims[i];
+        std::memset(&d, 0, sizeof(d));
+        d.width = 16 + (int32_t)i;
+        d.height = 16;
+        d.row_stride = 3 * d.width;
+        d.pixel_stride = 3;
+    }
+    std::vector<cahost::Shape> shapes(B);
+    std::vector<uint8_t> image;
+    cahost::Plan proto;
+    if (ok) {
+        int rc = cahost::plan_layout(ctx, dims.data(), (int32_t)B, cfg->params, lut, sg_len,
+                                     shapes.data(), (int32_t)B, &proto, &s->layout, nullptr, 0);
+        if (rc == CA_OK) {
+            image.resize(s->layout.image_bytes);
+            rc = cahost::plan_layout(ctx, dims.data(), (int32_t)B, cfg->params, lut, sg_len,
+                                     shapes.data(), (int32_t)B, &proto, &s->layout, image.data(),
+                                     image.size());
+        }
+        if (rc != CA_OK) {
+            ca_server_destroy(s);
+            return rc;
+        }
+    }
     s->batches.resize(ok ? (size_t)cfg->max_inflight : 0);
+    const size_t stage_bytes = s->layout.image_bytes;
     for (Batch &b : s->batches) {
-        ok = ok && hipMalloc(&b.res_dev, B * sizeof(ca_result)) == hipSuccess
+        b.plan.P = proto.P;
+        b.plan.groups = proto.groups;
+        b.plan.sg_len = proto.sg_len;
+        b.plan.dynamic = true;
+        ok = ok && hipMalloc(&b.plan.mem, s->layout.total) == hipSuccess
+             && hipMemcpy(b.plan.mem, image.data(), image.size(), hipMemcpyHostToDevice)
+                    == hipSuccess
+             && hipMalloc(&b.res_dev, B * sizeof(ca_result)) == hipSuccess
              && hipMalloc(&b.filt_dev, B * sizeof(float4)) == hipSuccess
              && hipMalloc(&b.runs_dev, B * sizeof(int4)) == hipSuccess
-             && hipHostMalloc(&b.fd_host, B * sizeof(ca::FrameDev)) == hipSuccess
+             && hipHostMalloc(&b.stage, stage_bytes) == hipSuccess
              && hipHostMalloc(&b.runs_host, B * sizeof(int4)) == hipSuccess
              && hipHostMalloc(&b.res_host, B * sizeof(ca_result)) == hipSuccess
              && hipHostMalloc(&b.filt_host, B * sizeof(float4)) == hipSuccess
              && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess;
+        if (ok)
+            cahost::plan_pointers(&b.plan, b.plan.mem, s->layout);
     }
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         ca_server_destroy(s);
@@ -443,13 +490,8 @@ void ca_server_destroy(ca_server *s)
     cahost::DeviceGuard guard(s->ctx->device);
     if (s->compute)
         (void)hipStreamSynchronize(s->compute);
-    for (Batch &b : s->batches) {
-        if (b.plan) {
-            cahost::free_plan(s->ctx, b.plan);
-            s->ctx->plans.erase(std::find(s->ctx->plans.begin(), s->ctx->plans.end(), b.plan));
-        }
+    for (Batch &b : s->batches)
         free_batch(b);
-    }
     for (auto &kv : s->streams)
         delete kv.second;
     (void)hipFree(s->arena_mem);
@@ -467,6 +509,12 @@ int ca_server_open(ca_server *s, int32_t id, int32_t W, int32_t H, int32_t *admi
     const size_t slot = frame_bytes(W, H);
     if (slot * (size_t)s->cfg.ring_slots > s->cfg.hbm_budget)
         return CA_E_INVAL;
+    // the strip kernels stage a line of the frame's longest extent in LDS
+    const size_t pitch = cahost::align_up((size_t)std::max(W, H), 16);
+    const int32_t sg_len = s->batches.empty() ? 0 : s->batches[0].plan.sg_len;
+    if (ca::strip_lds_bytes(sg_len, (int)pitch) > s->ctx->max_lds
+        || ca::fused_lds_bytes(sg_len, (int)pitch) > s->ctx->max_lds)
+        return CA_E_UNSUPPORTED;
     Stream *st = new (std::nothrow) Stream();
     if (!st)
         return CA_E_NOMEM;
@@ -474,10 +522,16 @@ int ca_server_open(ca_server *s, int32_t id, int32_t W, int32_t H, int32_t *admi
     st->W = W;
     st->H = H;
     st->slot_bytes = slot;
-    if (shape_index(s->shapes, W, H) < 0) {
-        s->shapes.push_back({W, H});
-        ++s->shapes_version;
+    // the stream's strip positions (Eq. 1), computed once here
+    const ca_params &p = s->cfg.params;
+    try {
+        st->table.assign((size_t)(p.n_hstrips + p.n_vstrips), 0);
+    } catch (...) {
+        delete st;
+        return CA_E_NOMEM;
     }
+    cahost::strip_positions(H, p.n_hstrips, p.alpha, st->table.data());
+    cahost::strip_positions(W, p.n_vstrips, p.alpha, st->table.data() + p.n_hstrips);
     s->streams[id] = st;
     s->order.push_back(st);
     cahost::DeviceGuard guard(s->ctx->device);

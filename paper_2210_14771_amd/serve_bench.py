@@ -5,7 +5,10 @@ line: per scorer the frames served, frames/s, p50/p99 latency from
 submission to the result being seen on the host, mean batch size, and the
 accuracy of the frames' own estimates and of the streams' filtered circles.
 
-    python -m paper_2210_14771_amd.serve_bench [--streams 48] [--seconds 0.3]
+Each scorer's server is fed in real time from its creation (no server fed a
+whole backlog at once runs before it in the process).
+
+    python -m paper_2210_14771_amd.serve_bench [--streams 48] [--seconds 0.4]
 """
 from __future__ import annotations
 
@@ -38,53 +41,33 @@ def accuracy(served, streams) -> dict:
     return out
 
 
-OPEN_ISSUE = ("serve_bench is switched off: its realtime run (after a warm-up server in the "
-              "same process) stopped making progress on the GPU three times; the cause is not "
-              "found yet, so this case is not run until it is")
-
-
-def main():
-    raise SystemExit(OPEN_ISSUE)
-
-
-def run_benchmark():
-    """The benchmark proper (not run while OPEN_ISSUE stands)."""
-    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--streams", type=int, default=48)
-    # a server has so far only been run to about 900 batches (0.4 s of the
-    # 48 streams); a 2 s run stopped making progress after 2178 batches, cause
-    # not found, so the default window stays well inside the tested range
-    ap.add_argument("--seconds", type=float, default=0.3)
-    ap.add_argument("--frames-per-stream", type=int, default=16)
-    ap.add_argument("--max-batch", type=int, default=64)
-    ap.add_argument("--budget-gib", type=float, default=4.0)
-    a = ap.parse_args()
-    import sys
+def run_benchmark(n_streams: int = 48, seconds: float = 0.4, frames_per_stream: int = 6,
+                  max_batch: int = 64, budget_gib: float = 4.0, log=None) -> dict:
+    """Per scorer one server, fed in real time from its creation: each
+    frame submitted at its arrival time, the server stepped until every
+    frame is served."""
     import torch
 
-    def log(msg):
-        print("# " + msg, file=sys.stderr, flush=True)
-
-    print(f"# rendering {a.streams} streams", flush=True)
-    streams = serve.make_streams(a.streams, a.frames_per_stream, a.seconds)
+    streams = serve.make_streams(n_streams, frames_per_stream, seconds, seed=1)
     est = api.Estimator(0)
     kw = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
-    line = {"metric": "serving latency, 48 mixed-resolution streams", "streams": a.streams,
-            "seconds": a.seconds,
-            "arrival_fps": float(sum(len(s.arrivals) for s in streams) / a.seconds)}
+    n_frames = sum(len(s.arrivals) for s in streams)
+    line = {"metric": f"serving latency, {n_streams} mixed-resolution streams",
+            "streams": n_streams, "seconds": seconds, "frames": n_frames,
+            "arrival_fps": n_frames / seconds,
+            "shapes": [f"{w}x{h}" for w, h in serve.SERVE_SHAPES],
+            "latency": "submission to the result seen on the host"}
     runs = [("plain", dict(kw))]
     model = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE)
     if os.path.exists(model):
         est.set_model(train_scorer.load_model(model))
         runs.append(("learned", dict(kw, scorer=1, fallback_inlier_frac=0.5)))
     for name, params in runs:
-        cfg = serve.server_config(max_batch=a.max_batch, hbm_budget=int(a.budget_gib * (1 << 30)),
+        cfg = serve.server_config(max_batch=max_batch, hbm_budget=int(budget_gib * (1 << 30)),
                                   **params)
         srv = serve.Server(est, cfg)
-        serve.run(srv, streams, realtime=False, timeout_s=60, progress=log)   # warm-up
-        srv.close()
-        srv = serve.Server(est, cfg)
-        print(f"# serving ({name})", flush=True)
+        if log:
+            log(f"serving ({name})")
         served, wall = serve.run(srv, streams, realtime=True, timeout_s=60, progress=log)
         stats = srv.stats()
         srv.close()
@@ -94,6 +77,24 @@ def run_benchmark():
         line[name] = rec
     torch.cuda.synchronize()
     est.close()
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--streams", type=int, default=48)
+    ap.add_argument("--seconds", type=float, default=0.4)
+    ap.add_argument("--frames-per-stream", type=int, default=6)
+    ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--budget-gib", type=float, default=4.0)
+    a = ap.parse_args()
+    import sys
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
+
+    line = run_benchmark(a.streams, a.seconds, a.frames_per_stream, a.max_batch, a.budget_gib,
+                         log)
     print(json.dumps(line), flush=True)
 
 
