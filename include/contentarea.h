@@ -100,6 +100,7 @@ typedef struct {
 
 #define CA_SCORER_HANDCRAFTED 0
 #define CA_SCORER_LEARNED 1
+#define CA_SCORER_LEARNED_2D 2  /* the paper's own network (ca_set_model_2d) */
 #define CA_REASON_FALLBACK 256
 
 /* Result per frame (32 bytes). */
@@ -203,6 +204,65 @@ int ca_get_model(ca_ctx *ctx, float *params_host, float *momentum_host, int32_t 
 /* Replace the SGD momentum (host array, model-file order), e.g. to resume
  * training from a checkpoint taken with ca_get_model.  Blocking. */
 int ca_set_momentum(ca_ctx *ctx, const float *momentum_host, int32_t n_params);
+
+/* The paper's own learned scorer (Section 2.2.4), scorer
+ * CA_SCORER_LEARNED_2D: three 3x3 convolutions with 8, 16 and 32 output
+ * features, each followed by a ReLU, a 1x1 convolution to one logit, score =
+ * sigmoid(logit), on five input channels per pixel, RGBXY: each colour v as
+ * bf16((v - mean_c) * inv_std_c) in float32 arithmetic (the training data's
+ * per-channel statistics, part of the model), the pixel coordinates as
+ * bf16((2x - (W - 1)) / (2 (W - 1))) and likewise for y, in [-0.5, 0.5] with
+ * 0 at the image centre.  Every layer's input is zero outside the frame
+ * ("same" zero padding).  Applied to strips seven lines thick, the
+ * receptive field, so a strip's scores are the whole-image network's output
+ * on the strip's line.  Weights and hidden activations are bfloat16, sums
+ * float32.
+ *
+ * Model file: CA_CNN2D_PARAMS float32 values in the order mean[3],
+ * inv_std[3], W1[8][5][3][3], b1[8], W2[16][8][3][3], b2[16],
+ * W3[32][16][3][3], b3[32], w4[32], b4[1] (W[out][in][dy][dx], channels
+ * R, G, B, X, Y); weights are rounded to bfloat16 when loaded.  The
+ * normaliser (the first 6 values) is not trained: its gradient is zero. */
+#define CA_CNN2D_PARAMS 6215
+
+/* Load (host pointer) the model used by CA_SCORER_LEARNED_2D; as
+ * ca_set_model (master weights, zero momentum).  Blocking.  CA_E_INVAL for a
+ * wrong count, a non-finite value or a non-positive inv_std. */
+int ca_set_model_2d(ca_ctx *ctx, const float *params_host, int32_t n_params);
+
+/* As ca_get_model and ca_set_momentum, for the 2-D model.  Blocking. */
+int ca_get_model_2d(ca_ctx *ctx, float *params_host, float *momentum_host, int32_t n_params);
+int ca_set_momentum_2d(ca_ctx *ctx, const float *momentum_host, int32_t n_params);
+
+/* Logits of the CA_CNN_OUTPUTS central positions (8 .. 119) of n rendered
+ * windows under the 2-D model.
+ *   windows_dev  uint8 [n][8][CA_CNN_WINDOW][3]: lines line-3 .. line+4 of
+ *                a strip (clamped to the frame; the network uses the first 7)
+ *   geom_dev     int32 [n][8]: horizontal (1: the strip is a row), line,
+ *                start (frame position of window position 0), frame width,
+ *                frame height, 0, 0, 0
+ *   range_dev    int32 [n][2]: window positions [lo, hi) inside the strip
+ *   logits_dev   float [n][CA_CNN_OUTPUTS]
+ * Enqueued on `stream`.  Needs ca_set_model_2d. */
+int ca_cnn2d_window_logits(ca_ctx *ctx, const uint8_t *windows_dev, const int32_t *geom_dev,
+                           const int32_t *range_dev, int32_t n_windows, float *logits_dev,
+                           void *stream);
+
+/* Gradients of the 2-D model, as ca_cnn_gradients (the same loss over the
+ * central positions of windows, the same argument meanings, plus geom_dev as
+ * for ca_cnn2d_window_logits); grad_dev holds CA_CNN2D_PARAMS floats in
+ * model-file order.  The backward pass stores its signals in bfloat16 and
+ * sums in float32.  The calls of one context share a gradient workspace:
+ * calls that overlap on different streams race. */
+int ca_cnn2d_gradients(ca_ctx *ctx, const uint8_t *windows_dev, const int32_t *geom_dev,
+                       const int32_t *range_dev, const float *target_dev,
+                       const float *weight_dev, int32_t n_windows, float scale, float *grad_dev,
+                       float *loss_dev, void *stream);
+
+/* One SGD step with momentum on the 2-D model's master weights (as
+ * ca_cnn_sgd_step), then the device model is rebuilt from them. */
+int ca_cnn2d_sgd_step(ca_ctx *ctx, const float *grad_dev, float lr, float momentum,
+                      void *stream);
 
 /* Training (Section 2.2.4: soft binary cross entropy against blurred edge
  * labels, SGD).  Gradients, with respect to the master weights, of

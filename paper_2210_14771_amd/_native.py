@@ -27,12 +27,16 @@ EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
            "ca_graph_destroy", "ca_set_model", "ca_get_model", "ca_set_momentum",
            "ca_cnn_window_logits", "ca_cnn_gradients", "ca_cnn_sgd_step", "ca_selftest_mfma",
+           "ca_set_model_2d", "ca_get_model_2d", "ca_set_momentum_2d", "ca_cnn2d_window_logits",
+           "ca_cnn2d_gradients", "ca_cnn2d_sgd_step",
            "ca_autotune", "ca_get_tuning", "ca_server_create", "ca_server_destroy",
            "ca_server_open", "ca_server_close", "ca_server_submit", "ca_server_step",
            "ca_server_stats",
            "ca_error_string", "ca_version")
 CA_SCORER_HANDCRAFTED = 0
 CA_SCORER_LEARNED = 1
+CA_SCORER_LEARNED_2D = 2
+CA_CNN2D_PARAMS = 6215
 CA_REASON_FALLBACK = 256
 CA_CNN_PARAMS = 12273
 CA_CNN_WINDOW = 128
@@ -147,6 +151,12 @@ def lib() -> C.CDLL:
         L.ca_cnn_gradients.argtypes = [vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
         L.ca_cnn_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
         L.ca_selftest_mfma.argtypes = [vp, vp, vp]
+        L.ca_set_model_2d.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.ca_get_model_2d.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_float), i32]
+        L.ca_set_momentum_2d.argtypes = [vp, C.POINTER(C.c_float), i32]
+        L.ca_cnn2d_window_logits.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.ca_cnn2d_gradients.argtypes = [vp, vp, vp, vp, vp, vp, i32, C.c_float, vp, vp, vp]
+        L.ca_cnn2d_sgd_step.argtypes = [vp, vp, C.c_float, C.c_float, vp]
         L.ca_autotune.argtypes = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params), i32, vp,
                                   C.POINTER(C.c_int32)]
         L.ca_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]

@@ -277,6 +277,83 @@ class Estimator:
                                         float(momentum), C.c_void_p(s.cuda_stream)),
                 "ca_cnn_sgd_step")
 
+    # the paper's own 2-D scorer (CA_SCORER_LEARNED_2D)
+
+    def set_model_2d(self, params) -> None:
+        """Load the 2-D scorer (CA_CNN2D_PARAMS float32 values, model-file order)."""
+        import numpy as np
+        a = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        N.check(N.lib().ca_set_model_2d(self._ctx, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                        a.size), "ca_set_model_2d")
+
+    def get_model_2d(self, with_momentum: bool = False):
+        import numpy as np
+        prm = np.empty(N.CA_CNN2D_PARAMS, dtype=np.float32)
+        mom = np.empty(N.CA_CNN2D_PARAMS, dtype=np.float32) if with_momentum else None
+        fp = C.POINTER(C.c_float)
+        N.check(N.lib().ca_get_model_2d(self._ctx, prm.ctypes.data_as(fp),
+                                        mom.ctypes.data_as(fp) if mom is not None else None,
+                                        prm.size), "ca_get_model_2d")
+        return (prm, mom) if with_momentum else prm
+
+    def set_momentum_2d(self, momentum) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(momentum, dtype=np.float32).ravel()
+        N.check(N.lib().ca_set_momentum_2d(self._ctx, a.ctypes.data_as(C.POINTER(C.c_float)),
+                                           a.size), "ca_set_momentum_2d")
+
+    @staticmethod
+    def _windows_2d(windows, geom, ranges):
+        if windows.dtype != torch.uint8 or tuple(windows.shape[1:]) != (8, N.CA_CNN_WINDOW, 3):
+            raise ValueError("windows must be uint8 [n, 8, 128, 3]")
+        n = windows.shape[0]
+        if tuple(geom.shape) != (n, 8) or tuple(ranges.shape) != (n, 2):
+            raise ValueError("geom must be [n, 8] and ranges [n, 2]")
+        return (windows.contiguous(), geom.to(torch.int32).contiguous(),
+                ranges.to(torch.int32).contiguous(), n)
+
+    def cnn2d_window_logits(self, windows: torch.Tensor, geom: torch.Tensor, ranges: torch.Tensor,
+                            stream=None) -> torch.Tensor:
+        """Logits [n, 112] of the 2-D scorer on uint8 windows [n, 8, 128, 3]
+        with int32 geometry [n, 8] and ranges [n, 2]."""
+        windows, geom, ranges, n = self._windows_2d(windows, geom, ranges)
+        z = torch.empty((n, N.CA_CNN_OUTPUTS), dtype=torch.float32, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        vp = C.c_void_p
+        N.check(N.lib().ca_cnn2d_window_logits(self._ctx, vp(windows.data_ptr()),
+                                               vp(geom.data_ptr()), vp(ranges.data_ptr()), n,
+                                               vp(z.data_ptr()), vp(s.cuda_stream)),
+                "ca_cnn2d_window_logits")
+        return z
+
+    def cnn2d_gradients(self, windows: torch.Tensor, geom: torch.Tensor, ranges: torch.Tensor,
+                        targets: torch.Tensor, weights: torch.Tensor, scale: float, stream=None):
+        """(grad [CA_CNN2D_PARAMS], loss [1]) device tensors of the weighted soft BCE."""
+        windows, geom, ranges, n = self._windows_2d(windows, geom, ranges)
+        for t, name in ((targets, "targets"), (weights, "weights")):
+            if t.dtype != torch.float32 or tuple(t.shape) != (n, N.CA_CNN_OUTPUTS):
+                raise ValueError(f"{name} must be float32 [n, {N.CA_CNN_OUTPUTS}]")
+        targets = targets.contiguous()
+        weights = weights.contiguous()
+        grad = torch.empty(N.CA_CNN2D_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        vp = C.c_void_p
+        N.check(N.lib().ca_cnn2d_gradients(self._ctx, vp(windows.data_ptr()), vp(geom.data_ptr()),
+                                           vp(ranges.data_ptr()), vp(targets.data_ptr()),
+                                           vp(weights.data_ptr()), n, float(scale),
+                                           vp(grad.data_ptr()), vp(loss.data_ptr()),
+                                           vp(s.cuda_stream)), "ca_cnn2d_gradients")
+        return grad, loss
+
+    def cnn2d_sgd_step(self, grad: torch.Tensor, lr: float, momentum: float, stream=None) -> None:
+        if grad.dtype != torch.float32 or grad.numel() != N.CA_CNN2D_PARAMS or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous float32 tensor of CA_CNN2D_PARAMS values")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        N.check(N.lib().ca_cnn2d_sgd_step(self._ctx, C.c_void_p(grad.data_ptr()), float(lr),
+                                          float(momentum), C.c_void_p(s.cuda_stream)),
+                "ca_cnn2d_sgd_step")
+
     def selftest_mfma(self) -> torch.Tensor:
         out = torch.empty((16, 16), dtype=torch.float32, device=self.device)
         s = torch.cuda.current_stream(self.device)

@@ -97,7 +97,8 @@ int validate(const ca_frame_desc *dims, int32_t n, const ca_params &p)
         return CA_E_INVAL;
     if (p.refine_iters < 0 || p.refine_iters > 64 || (p.sampler != 0 && p.sampler != 1))
         return CA_E_INVAL;
-    if (p.scorer != CA_SCORER_HANDCRAFTED && p.scorer != CA_SCORER_LEARNED)
+    if (p.scorer != CA_SCORER_HANDCRAFTED && p.scorer != CA_SCORER_LEARNED
+        && p.scorer != CA_SCORER_LEARNED_2D)
         return CA_E_INVAL;
     if (!(p.fallback_inlier_frac >= 0.0f && p.fallback_inlier_frac <= 1.0f))
         return CA_E_INVAL;
@@ -385,7 +386,7 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     ra.r_max = p.r_max;
     ra.d_max = p.d_max;
     ra.t_ps = (float)p.t_ps;
-    ra.t_px = p.scorer == CA_SCORER_LEARNED ? 0 : p.t_px;  // Table A1: t_px is handcrafted only
+    ra.t_px = p.scorer != CA_SCORER_HANDCRAFTED ? 0 : p.t_px;  // Table A1: t_px is handcrafted only
     ra.P = pl->P;
     ra.attempts = p.ransac_attempts;
     ra.refine = p.refine_iters;
@@ -430,6 +431,7 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     // strips then RANSAC for frames [f0, f1) on stream st
     const int S = p.n_hstrips + p.n_vstrips;
     const bool learned = p.scorer == CA_SCORER_LEARNED;
+    const bool learned2d = p.scorer == CA_SCORER_LEARNED_2D;
     auto launch_range = [&](int32_t f0, int32_t f1, hipStream_t st, hipEvent_t mid) {
         ca::StripArgs a2 = sa;
         a2.frame0 = f0;
@@ -438,7 +440,20 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
         ca::RansacArgs r2 = ra;
         r2.frame0 = f0;
         bool ok;
-        if (learned) {
+        if (learned2d) {
+            ca::Cnn2dStripArgs c;
+            c.frames = frames;
+            c.fd = pl->fd;
+            c.strips = pl->strips;
+            c.model = ctx->model2d;
+            c.cand = sa.cand;
+            c.n_h = p.n_hstrips;
+            c.n_v = p.n_vstrips;
+            c.n_items = a2.n_items;
+            c.per_xcd = a2.per_xcd;
+            c.frame0 = f0;
+            ok = ca::launch_cnn2d_strips(c, st) == hipSuccess;
+        } else if (learned) {
             ca::CnnStripArgs c;
             c.frames = frames;
             c.fd = pl->fd;
@@ -512,7 +527,7 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
             bool timed)
 {
     int rc = enqueue_one(ctx, pl, frames, n, p, points_out, attempts_out, out, s, timed);
-    if (rc != CA_OK || p.scorer != CA_SCORER_LEARNED || !(p.fallback_inlier_frac > 0.0f))
+    if (rc != CA_OK || p.scorer == CA_SCORER_HANDCRAFTED || !(p.fallback_inlier_frac > 0.0f))
         return rc;
     ca_params h = p;
     h.scorer = CA_SCORER_HANDCRAFTED;
@@ -543,7 +558,8 @@ int run(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, int32_t n
     int rc = validate(dims, n, p);
     if (rc != CA_OK)
         return rc;
-    if (p.scorer == CA_SCORER_LEARNED && !ctx->model)
+    if ((p.scorer == CA_SCORER_LEARNED && !ctx->model)
+        || (p.scorer == CA_SCORER_LEARNED_2D && !ctx->model2d))
         return CA_E_INVAL;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
@@ -672,6 +688,9 @@ void ca_destroy(ca_ctx *ctx)
             (void)hipFree(ctx->train);
         if (ctx->partial)
             (void)hipFree(ctx->partial);
+        (void)hipFree(ctx->model2d);
+        (void)hipFree(ctx->train2d);
+        (void)hipFree(ctx->partial2d);
     }
     delete ctx;
 }
@@ -777,7 +796,8 @@ int ca_graph_create(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dim
         p = *params;
     else
         ca_default_params(&p);
-    if (p.scorer == CA_SCORER_LEARNED && !ctx->model)
+    if ((p.scorer == CA_SCORER_LEARNED && !ctx->model)
+        || (p.scorer == CA_SCORER_LEARNED_2D && !ctx->model2d))
         return CA_E_INVAL;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
@@ -994,6 +1014,140 @@ int ca_cnn_window_logits(ca_ctx *ctx, const uint8_t *win, const int32_t *range, 
         return CA_E_DEVICE;
     return ca::launch_cnn_windows(ctx->model, win, range, z, n, static_cast<hipStream_t>(stream))
                    == hipSuccess
+               ? CA_OK
+               : CA_E_DEVICE;
+}
+
+// ---------------------------------------- the paper's 2-D scorer (2.2.4) --
+
+int ca_set_model_2d(ca_ctx *ctx, const float *prm, int32_t n)
+{
+    if (!ctx || !prm || n != CA_CNN2D_PARAMS || !finite_all(prm, n))
+        return CA_E_INVAL;
+    for (int c = 0; c < 3; ++c)
+        if (!(prm[3 + c] > 0.0f))
+            return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (!ctx->model2d && hipMalloc(&ctx->model2d, ca::kC2ModelBytes) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->model2d = nullptr;
+        return CA_E_NOMEM;
+    }
+    if (!ctx->train2d && hipMalloc(&ctx->train2d, 2 * sizeof(float) * ca::kC2Params) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->train2d = nullptr;
+        return CA_E_NOMEM;
+    }
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(ctx->train2d, prm, (size_t)n * sizeof(float), hipMemcpyHostToDevice)
+               != hipSuccess
+        || hipMemset(ctx->train2d + ca::kC2Params, 0, (size_t)n * sizeof(float)) != hipSuccess
+        || ca::launch_cnn2d_pack(ctx->train2d, ctx->model2d, nullptr) != hipSuccess
+        || hipDeviceSynchronize() != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_get_model_2d(ca_ctx *ctx, float *prm, float *mom, int32_t n)
+{
+    if (!ctx || !prm || n != CA_CNN2D_PARAMS || !ctx->train2d)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(prm, ctx->train2d, (size_t)n * sizeof(float), hipMemcpyDeviceToHost)
+               != hipSuccess)
+        return CA_E_DEVICE;
+    if (mom && hipMemcpy(mom, ctx->train2d + ca::kC2Params, (size_t)n * sizeof(float),
+                         hipMemcpyDeviceToHost) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_set_momentum_2d(ca_ctx *ctx, const float *mom, int32_t n)
+{
+    if (!ctx || !mom || n != CA_CNN2D_PARAMS || !ctx->train2d || !finite_all(mom, n))
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess
+        || hipMemcpy(ctx->train2d + ca::kC2Params, mom, (size_t)n * sizeof(float),
+                     hipMemcpyHostToDevice) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_cnn2d_window_logits(ca_ctx *ctx, const uint8_t *win, const int32_t *geom,
+                           const int32_t *range, int32_t n, float *z, void *stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!win || !geom || !range || !z)))
+        return CA_E_INVAL;
+    if (!ctx->model2d)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return ca::launch_cnn2d_windows(ctx->model2d, win, geom, range, z, n,
+                                    static_cast<hipStream_t>(stream)) == hipSuccess
+               ? CA_OK
+               : CA_E_DEVICE;
+}
+
+int ca_cnn2d_gradients(ca_ctx *ctx, const uint8_t *win, const int32_t *geom, const int32_t *range,
+                       const float *target, const float *weight, int32_t n, float scale,
+                       float *grad, float *loss, void *stream)
+{
+    if (!ctx || n < 0 || !grad || !loss || !std::isfinite(scale)
+        || (n > 0 && (!win || !geom || !range || !target || !weight)))
+        return CA_E_INVAL;
+    if (!ctx->model2d)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    if (!ctx->partial2d) {
+        const int grid = ca::cnn2d_grad_blocks_per_cu() * (ctx->n_cu > 0 ? ctx->n_cu : 256);
+        if (hipMalloc(&ctx->partial2d, (size_t)grid * ca::kC2GradStride * sizeof(float))
+            != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->partial2d = nullptr;
+            return CA_E_NOMEM;
+        }
+        ctx->grad2d_grid = grid;
+    }
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int grid = n < ctx->grad2d_grid ? (n > 0 ? n : 1) : ctx->grad2d_grid;
+    ca::Cnn2dTrainArgs a;
+    a.model = ctx->model2d;
+    a.win = win;
+    a.geom = geom;
+    a.range = range;
+    a.target = target;
+    a.weight = weight;
+    a.partial = ctx->partial2d;
+    a.scale = scale;
+    a.n = n;
+    if (ca::launch_cnn2d_grad(a, grid, st) != hipSuccess
+        || ca::launch_cnn2d_reduce(ctx->partial2d, grid, grad, loss, st) != hipSuccess)
+        return CA_E_DEVICE;
+    return CA_OK;
+}
+
+int ca_cnn2d_sgd_step(ca_ctx *ctx, const float *grad, float lr, float mu, void *stream)
+{
+    if (!ctx || !grad || !std::isfinite(lr) || !std::isfinite(mu))
+        return CA_E_INVAL;
+    if (!ctx->train2d)
+        return CA_E_INVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return CA_E_DEVICE;
+    return ca::launch_cnn2d_update(ctx->train2d, ctx->train2d + ca::kC2Params, grad, lr, mu,
+                                   ctx->model2d, static_cast<hipStream_t>(stream)) == hipSuccess
                ? CA_OK
                : CA_E_DEVICE;
 }

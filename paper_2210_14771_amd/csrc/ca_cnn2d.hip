@@ -1,0 +1,776 @@
+// gfx950 kernels of the paper's own learned edge scorer (arXiv 2210.14771,
+// Section 2.2.4): three 3x3 convolutions with 8, 16 and 32 output features,
+// each followed by a ReLU, a 1x1 convolution to one logit and a sigmoid, on
+// RGBXY input (colours normalised by the training data's per-channel mean
+// and standard deviation, pixel coordinates normalised to [-0.5, 0.5] about
+// the image centre), applied to strips seven lines thick (the network's
+// receptive field), so a strip's scores are the whole-image network's output
+// on the strip's centre line.
+//
+// A strip is processed in windows of 128 positions: band lines 0..6 (the
+// strip line -3 .. +3) of the input, lines 1..5 of layer 1, 2..4 of layer 2
+// and line 3 of layer 3.  Each layer is one GEMM per output line on
+// v_mfma_f32_16x16x32_bf16: activations are stored position-major
+// ([line][position][channel], channels contiguous, one zero guard position
+// at each end), so the 8 channels of one tap at one position are one
+// 16-byte LDS load, and K = (3 da + dl) C_pad + c walks the 3x3 taps.  For a
+// vertical strip the band's lines are frame columns: the weights' two
+// spatial axes swap roles, so the model block holds both orientations.
+// Every layer's input is zero outside the frame and beyond the strip ends
+// ("same" zero padding of the whole-image network).  Weights and hidden
+// activations are bfloat16, sums are float32 MFMA accumulators.
+#include "ca_cnn.h"
+
+namespace ca {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPos = kC2Win + 2;   // positions of a buffer line, guards included
+constexpr int kC2Halo = 3;         // the network's receptive-field radius
+constexpr int kC2Stride = kC2Win - 2 * kC2Halo;   // exact logits per strip window
+constexpr int kTrainHalo = 8;      // training windows carry logits 8 .. 119
+constexpr int kTrainOut = kC2Win - 2 * kTrainHalo;
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
+
+// LDS of the forward pass: input (7 lines, 8 channels: RGBXY and 3 zeros),
+// layer 1 (5 lines x 8), layer 2 (3 x 16), layer 3 (1 x 32), logits.
+struct alignas(16) FwdLds {
+    __bf16 x0[kC2Band * kPos * 8];
+    __bf16 h1[5 * kPos * 8];
+    __bf16 h2[3 * kPos * 16];
+    __bf16 h3[kPos * 32];
+    float z[kC2Win];
+};
+
+// The backward pass adds the signals at the pre-activations (ReLU and masks
+// applied) of layers 3, 2 and 1, the logit gradients and a zero line.
+struct alignas(16) GradLds {
+    FwdLds f;
+    __bf16 dp3[kPos * 32];
+    __bf16 dp2[3 * kPos * 16];
+    __bf16 dp1[5 * kPos * 8];
+    __bf16 zero[kPos * 32];
+    __bf16 ones[4];
+    float dz[kC2Win];
+    float loss[kBlock / 64];
+};
+
+// Clear a buffer (both guards included); a workgroup-wide loop.
+__device__ void clear(__bf16 *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += kBlock)
+        p[i] = to_bf16(0.0f);
+}
+
+// One 3x3 convolution layer over a window as GEMMs, one per output line i:
+// acc[m][n] = sum_k A[m][k] B_i[k][n] with B_i[(3 da + dl) CP + c][n] =
+// X[line i + da][n + dl - 1][c] (lines outside [x_lo, x_hi) read the zero
+// line); epi(i, m0, n, acc) receives rows m0 .. m0 + 3 of column n.
+template <int CP, int KP, int MT, int OUT_LINES, class Epi>
+__device__ void gemm3x3(const __bf16 *A, const __bf16 *X, int x_lo, int x_hi, const __bf16 *zero,
+                        Epi epi)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    constexpr int NT = kC2Win / 16;
+    constexpr int CB = CP / 8;
+    constexpr int G = 9 * CB;   // real 8-wide K groups; the rest have zero weights
+    const int kq = lane >> 4;
+    for (int tile = wv; tile < OUT_LINES * NT * MT; tile += kBlock / 64) {
+        const int mt = tile % MT;
+        const int nt = (tile / MT) % NT;
+        const int i = tile / (MT * NT);
+        const int m = mt * 16 + (lane & 15);
+        const int n = nt * 16 + (lane & 15);
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KP / 32; ++ks) {
+            int g = 4 * ks + kq;
+            g = g < G ? g : 0;
+            const int tap = g / CB, cb = g - CB * (g / CB);
+            const int da = tap / 3, dl = tap - 3 * (tap / 3);
+            const int line = i + da;
+            const __bf16 *src = (line >= x_lo && line < x_hi) ? X + (line - x_lo) * kPos * CP : zero;
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + m * KP + 32 * ks + 8 * kq);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(src + (n + dl) * CP + 8 * cb);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+        epi(i, mt * 16 + 4 * kq, n, acc);
+    }
+}
+
+// Input encoding of one band position: colours normalised, coordinates in
+// [-0.5, 0.5]; channels 5..7 are zero.  (x, y) is the pixel, (W, H) the frame.
+__device__ __forceinline__ void encode(__bf16 *dst, uint32_t r, uint32_t g, uint32_t b, int x,
+                                       int y, int W, int H, const float *fb)
+{
+    bf16x8 v;
+    v[0] = to_bf16(((float)r - fb[kC2FMean + 0]) * fb[kC2FInv + 0]);
+    v[1] = to_bf16(((float)g - fb[kC2FMean + 1]) * fb[kC2FInv + 1]);
+    v[2] = to_bf16(((float)b - fb[kC2FMean + 2]) * fb[kC2FInv + 2]);
+    v[3] = to_bf16((float)(2 * x - (W - 1)) / (float)(2 * (W - 1)));
+    v[4] = to_bf16((float)(2 * y - (H - 1)) / (float)(2 * (H - 1)));
+    v[5] = v[6] = v[7] = to_bf16(0.0f);
+    *reinterpret_cast<bf16x8 *>(dst) = v;
+}
+
+__device__ __forceinline__ bool line_in(uint32_t line_ok, int j) { return (line_ok >> j) & 1u; }
+
+// Forward pass of the window whose input is in L.x0: logits of all 128
+// positions into L.z (exact where the whole receptive field is inside the
+// window).  line_ok bit j: band line j lies in the frame; positions outside
+// [lo, hi) are beyond the strip.
+__device__ void forward(FwdLds &L, const __bf16 *A, const float *fb, uint32_t line_ok, int lo,
+                        int hi)
+{
+    gemm3x3<8, 96, 1, 5>(A + kC2A[0], L.x0, 0, kC2Band, nullptr,
+                         [&](int i, int m0, int n, const f32x4 &acc) {
+                             if (m0 >= 8)
+                                 return;
+                             const bool keep = line_in(line_ok, i + 1) && n >= lo && n < hi;
+                             bf16x4 o;
+#pragma unroll
+                             for (int j = 0; j < 4; ++j) {
+                                 const float v = fmaxf(acc[j] + fb[kC2FB[0] + m0 + j], 0.0f);
+                                 o[j] = to_bf16(keep ? v : 0.0f);
+                             }
+                             *reinterpret_cast<bf16x4 *>(L.h1 + (i * kPos + n + 1) * 8 + m0) = o;
+                         });
+    __syncthreads();
+    gemm3x3<8, 96, 1, 3>(A + kC2A[1], L.h1, 0, 5, nullptr,
+                         [&](int i, int m0, int n, const f32x4 &acc) {
+                             const bool keep = line_in(line_ok, i + 2) && n >= lo && n < hi;
+                             bf16x4 o;
+#pragma unroll
+                             for (int j = 0; j < 4; ++j) {
+                                 const float v = fmaxf(acc[j] + fb[kC2FB[1] + m0 + j], 0.0f);
+                                 o[j] = to_bf16(keep ? v : 0.0f);
+                             }
+                             *reinterpret_cast<bf16x4 *>(L.h2 + (i * kPos + n + 1) * 16 + m0) = o;
+                         });
+    __syncthreads();
+    gemm3x3<16, 160, 2, 1>(A + kC2A[2], L.h2, 0, 3, nullptr,
+                           [&](int, int m0, int n, const f32x4 &acc) {
+                               const bool keep = line_in(line_ok, 3) && n >= lo && n < hi;
+                               bf16x4 o;
+#pragma unroll
+                               for (int j = 0; j < 4; ++j) {
+                                   const float v = fmaxf(acc[j] + fb[kC2FB[2] + m0 + j], 0.0f);
+                                   o[j] = to_bf16(keep ? v : 0.0f);
+                               }
+                               *reinterpret_cast<bf16x4 *>(L.h3 + (n + 1) * 32 + m0) = o;
+                           });
+    __syncthreads();
+    const int n = threadIdx.x;
+    if (n < kC2Win) {
+        const __bf16 *h = L.h3 + (n + 1) * 32;
+        float z = fb[kC2FB4];
+#pragma unroll
+        for (int o = 0; o < 32; ++o)
+            z = fmaf(fb[kC2FW4 + o], (float)h[o], z);
+        L.z[n] = z;
+    }
+    __syncthreads();
+}
+
+// The input of a rendered window [8][128][3] (lines line-3 .. line+4,
+// clamped to the frame): band lines 0..6, zero outside the frame or strip.
+__device__ void load_window(FwdLds &L, const uint8_t *src, const int32_t *g, const float *fb,
+                            uint32_t line_ok, int lo, int hi)
+{
+    const bool hz = g[0] != 0;
+    const int line = g[1], start = g[2], W = g[3], H = g[4];
+    for (int i = threadIdx.x; i < kC2Band * kC2Win; i += kBlock) {
+        const int j = i / kC2Win, n = i - kC2Win * (i / kC2Win);
+        __bf16 *dst = L.x0 + (j * kPos + n + 1) * 8;
+        if (!line_in(line_ok, j) || n < lo || n >= hi) {
+            *reinterpret_cast<bf16x8 *>(dst) = bf16x8{};
+            continue;
+        }
+        const uint8_t *px = src + (j * kC2Win + n) * 3;
+        const int across = line - 3 + j, along = start + n;
+        encode(dst, px[0], px[1], px[2], hz ? along : across, hz ? across : along, W, H, fb);
+    }
+}
+
+__device__ __forceinline__ uint32_t band_lines(int line, int extent)
+{
+    uint32_t ok = 0;
+    for (int j = 0; j < kC2Band; ++j) {
+        const int r = line - 3 + j;
+        ok |= (r >= 0 && r < extent) ? (1u << j) : 0u;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// ----------------------------------------------------------- inference --
+
+// Learned candidates: one workgroup per (frame, strip) item, XCD-aware
+// (workgroup b takes item (b % 8) per_xcd + b / 8); the strip's windows in
+// turn, best pixel of each half (ties: outermost).
+__global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
+{
+    __shared__ FwdLds L;
+    __shared__ uint64_t s_best[kBlock / 64][2];
+    const int item = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+    if (item >= a.n_items || (int)(blockIdx.x >> 3) >= a.per_xcd)
+        return;
+    const int S = a.n_h + a.n_v;
+    const int f = uniform_int(a.frame0 + item / S);
+    const int st = uniform_int(item % S);
+    const FrameDev d = a.fd[f];
+    const uint8_t *frame = a.frames + d.offset;
+    const bool hz = st < a.n_h;
+    const int pos = uniform_int(a.strips[d.table + st]);
+    const int L_ = hz ? d.W : d.H;
+    const int extent = hz ? d.H : d.W;
+    const uint32_t line_ok = band_lines(pos, extent);
+    const __bf16 *A = reinterpret_cast<const __bf16 *>(a.model) + (hz ? 0 : kC2Orient);
+    const float *fb = reinterpret_cast<const float *>(a.model + kC2FloatsOff);
+    // guard positions stay zero (every window rewrites the rest)
+    clear(L.x0, kC2Band * kPos * 8);
+    clear(L.h1, 5 * kPos * 8);
+    clear(L.h2, 3 * kPos * 16);
+    uint64_t best[2] = {0, 0};
+    const int n_win = (L_ + kC2Stride - 1) / kC2Stride;
+    for (int w = 0; w < n_win; ++w) {
+        const int start = w * kC2Stride - kC2Halo;
+        const int lo = start >= 0 ? 0 : -start;
+        const int hi = L_ - start < kC2Win ? L_ - start : kC2Win;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kC2Band * kC2Win; i += kBlock) {
+            // horizontal: positions fastest (adjacent pixels of a row);
+            // vertical: lines fastest (adjacent pixels of a row)
+            const int j = hz ? i / kC2Win : i % kC2Band;
+            const int n = hz ? i % kC2Win : i / kC2Band;
+            __bf16 *dst = L.x0 + (j * kPos + n + 1) * 8;
+            if (!line_in(line_ok, j) || n < lo || n >= hi) {
+                *reinterpret_cast<bf16x8 *>(dst) = bf16x8{};
+                continue;
+            }
+            const int across = pos - 3 + j, along = start + n;
+            const int x = hz ? along : across, y = hz ? across : along;
+            const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
+            encode(dst, px[0], px[1], px[2], x, y, d.W, d.H, fb);
+        }
+        __syncthreads();
+        forward(L, A, fb, line_ok, lo, hi);
+        const int n = threadIdx.x;
+        const int p = start + n;
+        if (n >= kC2Halo && n < kC2Win - kC2Halo && p < L_) {
+            const float sc = sigmoid(L.z[n]);
+            const int half = p < (L_ >> 1) ? 0 : 1;
+            const int k = half == 0 ? p : L_ - 1 - p;
+            const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
+                                 | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
+            best[half] = best[half] > key ? best[half] : key;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        uint64_t v = best[half];
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            const uint64_t t = __shfl_xor(v, dd, 64);
+            v = v > t ? v : t;
+        }
+        if (lane == 0)
+            s_best[wv][half] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int half = threadIdx.x;
+        uint64_t bb = s_best[0][half];
+        for (int w2 = 1; w2 < kBlock / 64; ++w2)
+            bb = bb > s_best[w2][half] ? bb : s_best[w2][half];
+        const int k = (int)(0xFFFFFFFFu - (uint32_t)bb);
+        const int i = half == 0 ? k : L_ - 1 - k;
+        ca_point pt;
+        pt.x = (int16_t)(hz ? i : pos);
+        pt.y = (int16_t)(hz ? pos : i);
+        pt.score = __uint_as_float((uint32_t)(bb >> 32));
+        a.cand[(int64_t)f * (2 * S) + 2 * st + half] = pt;
+    }
+}
+
+// Logits of positions 8 .. 119 of rendered windows (one workgroup per window,
+// grid-stride).
+__global__ __launch_bounds__(kBlock) void k_cnn2d_windows(const uint8_t *model,
+                                                          const uint8_t *win,
+                                                          const int32_t *geom,
+                                                          const int32_t *range, float *z_out,
+                                                          int n_windows)
+{
+    __shared__ FwdLds L;
+    const float *fb = reinterpret_cast<const float *>(model + kC2FloatsOff);
+    clear(L.x0, kC2Band * kPos * 8);
+    clear(L.h1, 5 * kPos * 8);
+    clear(L.h2, 3 * kPos * 16);
+    for (int wi = blockIdx.x; wi < n_windows; wi += gridDim.x) {
+        const int32_t *g = geom + 8 * wi;
+        const bool hz = g[0] != 0;
+        const int lo = uniform_int(range[2 * wi]), hi = uniform_int(range[2 * wi + 1]);
+        const uint32_t line_ok = band_lines(g[1], hz ? g[4] : g[3]);
+        __syncthreads();
+        load_window(L, win + (int64_t)wi * (8 * kC2Win * 3), g, fb, line_ok, lo, hi);
+        __syncthreads();
+        forward(L, reinterpret_cast<const __bf16 *>(model) + (hz ? 0 : kC2Orient), fb, line_ok,
+                lo, hi);
+        const int n = threadIdx.x;
+        if (n >= kTrainHalo && n < kC2Win - kTrainHalo)
+            z_out[(int64_t)wi * kTrainOut + n - kTrainHalo] = L.z[n];
+    }
+}
+
+// ------------------------------------------------------------- training --
+//
+// Per window: the forward pass; dz = scale w (sigmoid(z) - t) on the
+// central positions inside the strip; the signals at the pre-activations
+// dP3 = [h3 > 0] w4 dz, dP2 = [h2 > 0] (flipped-W3 convolution of dP3),
+// dP1 = [h1 > 0] (flipped-W2 convolution of dP2), each stored in bfloat16
+// (the input-gradient convolutions are forward-shaped GEMMs on MFMA); then
+// the weight and bias gradients as sums over the window's positions, in
+// float32 registers that every thread keeps across the windows of its
+// workgroup.  Work units of 4 output channels x 4 inputs (one 3x3 tap of a
+// layer, frame orientation, one output line): thread t holds units t, t+256,
+// t+512 in the order
+//   [0, 288)    layer 3: o4 (8), tap (9), c4 (4)
+//   [288, 504)  layer 2: o4 (4), tap (9), c4 (2), line (3)
+//   [504, 684)  layer 1: o4 (2), tap (9), c4 (2), line (5)
+//   [684, 714)  biases: layer 3 o4 (8); layer 2 o4 (4) x line (3); layer 1
+//               o4 (2) x line (5)
+//   [714, 723)  w4 o4 (8), b4.
+// Each workgroup writes its unit sums; k_cnn2d_reduce adds them up in a
+// fixed order (deterministic) and maps them to model-file order.
+
+struct Unit {
+    int kind;         // 0 product, 1 bias, 2 w4 / b4 (from the logit gradients)
+    int p_off, p_step;   // dP (or h3): 4 channels at p_off + n p_step
+    int q_off, q_step;   // input: 4 channels at q_off + n q_step (ones for a bias)
+    bool is_b4;
+};
+
+__device__ Unit unit_of(int u, bool hz, const GradLds &G)
+{
+    // offsets are in bfloat16 elements from the start of GradLds
+    const __bf16 *base = reinterpret_cast<const __bf16 *>(&G);
+    auto off = [&](const __bf16 *p) { return (int)(p - base); };
+    Unit U{0, 0, 0, 0, 0, false};
+    auto taps = [&](int tap, int &da, int &dl) {
+        const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+        da = hz ? dy : dx;
+        dl = hz ? dx : dy;
+    };
+    int da = 0, dl = 0;
+    if (u < 288) {
+        const int o4 = u % 8, tap = (u / 8) % 9, c4 = u / 72;
+        taps(tap, da, dl);
+        U.p_off = off(G.dp3 + 32 + 4 * o4);
+        U.p_step = 32;
+        U.q_off = off(G.f.h2 + (da * kPos + dl) * 16 + 4 * c4);
+        U.q_step = 16;
+    } else if (u < 504) {
+        const int v = u - 288;
+        const int o4 = v % 4, tap = (v / 4) % 9, c4 = (v / 36) % 2, r = v / 72;
+        taps(tap, da, dl);
+        U.p_off = off(G.dp2 + (r * kPos + 1) * 16 + 4 * o4);
+        U.p_step = 16;
+        U.q_off = off(G.f.h1 + ((r + da) * kPos + dl) * 8 + 4 * c4);
+        U.q_step = 8;
+    } else if (u < 684) {
+        const int v = u - 504;
+        const int o4 = v % 2, tap = (v / 2) % 9, c4 = (v / 18) % 2, r = v / 36;
+        taps(tap, da, dl);
+        U.p_off = off(G.dp1 + (r * kPos + 1) * 8 + 4 * o4);
+        U.p_step = 8;
+        U.q_off = off(G.f.x0 + ((r + da) * kPos + dl) * 8 + 4 * c4);
+        U.q_step = 8;
+    } else if (u < 714) {
+        U.kind = 1;
+        U.q_off = off(G.ones);
+        U.q_step = 0;
+        if (u < 692) {
+            U.p_off = off(G.dp3 + 32 + 4 * (u - 684));
+            U.p_step = 32;
+        } else if (u < 704) {
+            const int v = u - 692;
+            U.p_off = off(G.dp2 + ((v / 4) * kPos + 1) * 16 + 4 * (v % 4));
+            U.p_step = 16;
+        } else {
+            const int v = u - 704;
+            U.p_off = off(G.dp1 + ((v / 2) * kPos + 1) * 8 + 4 * (v % 2));
+            U.p_step = 8;
+        }
+    } else {
+        U.kind = 2;
+        U.is_b4 = u == 722;
+        U.p_off = off(G.f.h3 + 32 + 4 * (u - 714));
+        U.p_step = 32;
+    }
+    return U;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cnn2d_grad(Cnn2dTrainArgs a)
+{
+    extern __shared__ __align__(16) uint8_t c2_smem[];
+    GradLds &G = *reinterpret_cast<GradLds *>(c2_smem);
+    FwdLds &L = G.f;
+    const __bf16 *lds = reinterpret_cast<const __bf16 *>(&G);
+    const float *fb = reinterpret_cast<const float *>(a.model + kC2FloatsOff);
+    clear(L.x0, kC2Band * kPos * 8);
+    clear(L.h1, 5 * kPos * 8);
+    clear(L.h2, 3 * kPos * 16);
+    clear(L.h3, kPos * 32);
+    clear(G.dp3, kPos * 32);
+    clear(G.dp2, 3 * kPos * 16);
+    clear(G.dp1, 5 * kPos * 8);
+    clear(G.zero, kPos * 32);
+    if (threadIdx.x < 4)
+        G.ones[threadIdx.x] = to_bf16(1.0f);
+    float acc[3][16];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            acc[s][e] = 0.0f;
+    float loss = 0.0f;
+    const int t = threadIdx.x;
+    for (int wi = blockIdx.x; wi < a.n; wi += gridDim.x) {
+        const int32_t *g = a.geom + 8 * wi;
+        const bool hz = g[0] != 0;
+        const int lo = uniform_int(a.range[2 * wi]), hi = uniform_int(a.range[2 * wi + 1]);
+        const uint32_t line_ok = band_lines(g[1], hz ? g[4] : g[3]);
+        const __bf16 *A = reinterpret_cast<const __bf16 *>(a.model) + (hz ? 0 : kC2Orient);
+        __syncthreads();
+        load_window(L, a.win + (int64_t)wi * (8 * kC2Win * 3), g, fb, line_ok, lo, hi);
+        __syncthreads();
+        forward(L, A, fb, line_ok, lo, hi);
+        // logit gradients and the loss (soft binary cross entropy)
+        if (t < kC2Win) {
+            float dz = 0.0f;
+            if (t >= kTrainHalo && t < kC2Win - kTrainHalo && t >= lo && t < hi) {
+                const int q = t - kTrainHalo;
+                const float tg = a.target[(int64_t)wi * kTrainOut + q];
+                const float wt = a.weight[(int64_t)wi * kTrainOut + q];
+                const float z = L.z[t];
+                const float s = sigmoid(z);
+                // -(t log s + (1 - t) log(1 - s)) = max(z, 0) - z t + log(1 + e^-|z|)
+                loss += a.scale * wt * (fmaxf(z, 0.0f) - z * tg + log1pf(__expf(-fabsf(z))));
+                dz = a.scale * wt * (s - tg);
+            }
+            G.dz[t] = dz;
+        }
+        __syncthreads();
+        // w4 and b4 (before h3 is overwritten)
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int u = t + kBlock * s;
+            if (u < 714 || u >= kC2Units)
+                continue;
+            const Unit U = unit_of(u, hz, G);
+            for (int n = 0; n < kC2Win; ++n) {
+                const float dz = G.dz[n];
+                if (U.is_b4) {
+                    acc[s][0] += dz;
+                } else {
+                    const bf16x4 h = *reinterpret_cast<const bf16x4 *>(lds + U.p_off + n * U.p_step);
+#pragma unroll
+                    for (int o = 0; o < 4; ++o)
+                        acc[s][4 * o] += (float)h[o] * dz;
+                }
+            }
+        }
+        // dP3 = [h3 > 0] w4 dz
+        for (int i = t; i < kC2Win * 32; i += kBlock) {
+            const int n = i >> 5, o = i & 31;
+            const float h = (float)L.h3[(n + 1) * 32 + o];
+            G.dp3[(n + 1) * 32 + o] = to_bf16(h > 0.0f ? fb[kC2FW4 + o] * G.dz[n] : 0.0f);
+        }
+        __syncthreads();
+        // dP2 = [h2 > 0] (flipped W3 * dP3): output lines 0..2 of layer 2;
+        // the dP3 line sits at band line 3, i.e. input line 2 of the GEMM
+        gemm3x3<32, 288, 1, 3>(A + kC2F3, G.dp3, 2, 3, G.zero,
+                               [&](int i, int m0, int n, const f32x4 &v) {
+                                   const __bf16 *h = L.h2 + (i * kPos + n + 1) * 16 + m0;
+                                   bf16x4 o;
+#pragma unroll
+                                   for (int j = 0; j < 4; ++j)
+                                       o[j] = to_bf16((float)h[j] > 0.0f ? v[j] : 0.0f);
+                                   *reinterpret_cast<bf16x4 *>(G.dp2 + (i * kPos + n + 1) * 16 + m0) = o;
+                               });
+        __syncthreads();
+        // dP1 = [h1 > 0] (flipped W2 * dP2): lines 0..4 of layer 1; dP2 lines
+        // are GEMM input lines 2..4
+        gemm3x3<16, 160, 1, 5>(A + kC2F2, G.dp2, 2, 5, G.zero,
+                               [&](int i, int m0, int n, const f32x4 &v) {
+                                   if (m0 >= 8)
+                                       return;
+                                   const __bf16 *h = L.h1 + (i * kPos + n + 1) * 8 + m0;
+                                   bf16x4 o;
+#pragma unroll
+                                   for (int j = 0; j < 4; ++j)
+                                       o[j] = to_bf16((float)h[j] > 0.0f ? v[j] : 0.0f);
+                                   *reinterpret_cast<bf16x4 *>(G.dp1 + (i * kPos + n + 1) * 8 + m0) = o;
+                               });
+        __syncthreads();
+        // weight and bias gradients
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int u = t + kBlock * s;
+            if (u >= 714)
+                continue;
+            const Unit U = unit_of(u, hz, G);
+            for (int n = 0; n < kC2Win; ++n) {
+                const bf16x4 p = *reinterpret_cast<const bf16x4 *>(lds + U.p_off + n * U.p_step);
+                const bf16x4 q = *reinterpret_cast<const bf16x4 *>(lds + U.q_off + n * U.q_step);
+#pragma unroll
+                for (int o = 0; o < 4; ++o)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[s][4 * o + c] += (float)p[o] * (float)q[c];
+            }
+        }
+    }
+    // loss: wave sums, then the workgroup's
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1)
+        loss += __shfl_xor(loss, dd, 64);
+    __syncthreads();
+    if ((t & 63) == 0)
+        G.loss[t >> 6] = loss;
+    __syncthreads();
+    float *out = a.partial + (int64_t)blockIdx.x * kC2GradStride;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int u = t + kBlock * s;
+        if (u < kC2Units)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                out[16 * u + e] = acc[s][e];
+    }
+    if (t == 0) {
+        float l = 0.0f;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2)
+            l += G.loss[w2];
+        out[16 * kC2Units] = l;
+    }
+}
+
+// Gradient in model-file order from the workgroups' unit sums (fixed order:
+// workgroups, then a layer's output lines); the normaliser gets zero.
+__global__ __launch_bounds__(kBlock) void k_cnn2d_reduce(const float *partial, int grid,
+                                                         float *grad, float *loss)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i > kC2Params)
+        return;
+    // the (unit, entry) pairs summed for parameter i
+    int u0 = -1, e0 = 0, step = 0, count = 0;
+    if (i == kC2Params) {
+        u0 = kC2Units;
+        count = 1;
+    } else if (i >= kC2FileW[0] && i < kC2FileB4) {
+        int l = 2;
+        while (l > 0 && i < kC2FileW[l])
+            --l;
+        constexpr int cin[3] = {5, 8, 16}, cout[3] = {8, 16, 32};
+        const int wn = cout[l] * cin[l] * 9;
+        if (i >= kC2FileW4) {
+            const int o = i - kC2FileW4;
+            u0 = 714 + o / 4;
+            e0 = 4 * (o % 4);
+            count = 1;
+        } else if (i < kC2FileW[l] + wn) {
+            const int r = i - kC2FileW[l];
+            const int o = r / (cin[l] * 9), c = (r / 9) % cin[l], tap = r % 9;
+            e0 = 4 * (o % 4) + c % 4;
+            if (l == 2) {
+                u0 = o / 4 + 8 * (tap + 9 * (c / 4));
+                count = 1;
+            } else if (l == 1) {
+                u0 = 288 + o / 4 + 4 * (tap + 9 * (c / 4));
+                step = 72;
+                count = 3;
+            } else {
+                u0 = 504 + o / 4 + 2 * (tap + 9 * (c / 4));
+                step = 36;
+                count = 5;
+            }
+        } else {
+            const int o = i - (kC2FileW[l] + wn);
+            e0 = 4 * (o % 4);
+            if (l == 2) {
+                u0 = 684 + o / 4;
+                count = 1;
+            } else if (l == 1) {
+                u0 = 692 + o / 4;
+                step = 4;
+                count = 3;
+            } else {
+                u0 = 704 + o / 4;
+                step = 2;
+                count = 5;
+            }
+        }
+    } else if (i == kC2FileB4) {
+        u0 = 722;
+        count = 1;
+    }
+    float v = 0.0f;
+    for (int g = 0; g < grid; ++g)
+        for (int k = 0; k < count; ++k)
+            v += partial[(int64_t)g * kC2GradStride + 16 * (u0 + k * step) + e0];
+    if (i == kC2Params)
+        *loss = v;
+    else
+        grad[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cnn2d_sgd(float *master, float *mom, const float *grad,
+                                                      float lr, float mu)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= kC2Params)
+        return;
+    const float m = mu * mom[i] + grad[i];
+    mom[i] = m;
+    master[i] -= lr * m;
+}
+
+// Device model block from the float32 master weights (file order); every
+// slot, padding included, is written.
+__global__ __launch_bounds__(kBlock) void k_cnn2d_pack(const float *master, uint8_t *model)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    constexpr int cin[3] = {5, 8, 16}, cout[3] = {8, 16, 32}, cp[3] = {8, 8, 16};
+    if (i < 2 * kC2Orient) {
+        const int orient = i / kC2Orient, e = i - kC2Orient * (i / kC2Orient);
+        float v = 0.0f;
+        int l, o, c, da, dl;
+        bool real = false;
+        if (e < kC2F2) {
+            l = e < kC2A[1] ? 0 : e < kC2A[2] ? 1 : 2;
+            const int r = e - kC2A[l];
+            const int m = r / kC2KP[l], k = r % kC2KP[l];
+            const int tap = k / cp[l];
+            c = k % cp[l];
+            o = m;
+            da = tap / 3;
+            dl = tap % 3;
+            real = m < cout[l] && tap < 9 && c < cin[l];
+        } else {
+            l = e < kC2F3 ? 1 : 2;
+            const int r = e - (l == 1 ? kC2F2 : kC2F3);
+            const int kp = l == 1 ? 160 : 288;
+            const int m = r / kp, k = r % kp;
+            const int tap = k / cout[l];
+            o = k % cout[l];
+            c = m;
+            da = 2 - tap / 3;
+            dl = 2 - tap % 3;
+            real = m < cin[l] && tap < 9;
+        }
+        if (real) {
+            const int dy = orient == 0 ? da : dl, dx = orient == 0 ? dl : da;
+            v = master[kC2FileW[l] + ((o * cin[l] + c) * 3 + dy) * 3 + dx];
+        }
+        reinterpret_cast<__bf16 *>(model)[i] = to_bf16(v);
+        return;
+    }
+    const int f = i - 2 * kC2Orient;
+    if (f >= 96)
+        return;
+    float *fb = reinterpret_cast<float *>(model + kC2FloatsOff);
+    float v = 0.0f;
+    if (f < 8)
+        v = master[kC2FileB[0] + f];
+    else if (f < 24)
+        v = master[kC2FileB[1] + f - 8];
+    else if (f < 56)
+        v = master[kC2FileB[2] + f - 24];
+    else if (f < 88)
+        v = (float)to_bf16(master[kC2FileW4 + f - 56]);
+    else if (f == 88)
+        v = master[kC2FileB4];
+    else if (f < 95)
+        v = master[f - 89];     // mean[3], inv_std[3]
+    fb[f] = v;
+}
+
+}  // namespace
+
+hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t s)
+{
+    if (a.n_items <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_cnn2d_strips, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn2d_windows(const uint8_t *model, const uint8_t *win, const int32_t *geom,
+                                const int32_t *range, float *z, int n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int grid = n < 2048 ? n : 2048;
+    hipLaunchKernelGGL(k_cnn2d_windows, dim3(grid), dim3(kBlock), 0, s, model, win, geom, range,
+                       z, n);
+    return hipGetLastError();
+}
+
+int cnn2d_grad_blocks_per_cu()
+{
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_cnn2d_grad, kBlock, sizeof(GradLds))
+            != hipSuccess
+        || b < 1) {
+        (void)hipGetLastError();
+        b = 1;
+    }
+    return b;
+}
+
+hipError_t launch_cnn2d_grad(const Cnn2dTrainArgs &a, int grid, hipStream_t s)
+{
+    if (grid <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cnn2d_grad, dim3(grid), dim3(kBlock), sizeof(GradLds), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn2d_reduce(const float *partial, int grid, float *grad_out, float *loss_out,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnn2d_reduce, dim3((kC2Params + 1 + kBlock - 1) / kBlock), dim3(kBlock),
+                       0, s, partial, grid, grad_out, loss_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn2d_update(float *master, float *momentum, const float *grad, float lr,
+                               float mom, uint8_t *model, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnn2d_sgd, dim3((kC2Params + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       master, momentum, grad, lr, mom);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_cnn2d_pack(master, model, s);
+}
+
+hipError_t launch_cnn2d_pack(const float *master, uint8_t *model, hipStream_t s)
+{
+    constexpr int slots = 2 * kC2Orient + 96;
+    hipLaunchKernelGGL(k_cnn2d_pack, dim3((slots + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       master, model);
+    return hipGetLastError();
+}
+
+}  // namespace ca

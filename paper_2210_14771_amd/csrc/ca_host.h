@@ -100,6 +100,10 @@ struct ca_ctx {
     float *train = nullptr;     // master weights [kCnnParams], then momentum [kCnnParams]
     float *partial = nullptr;   // gradient partials [grad_grid][kCnnGradStride]
     int grad_grid = 0;
+    uint8_t *model2d = nullptr;   // the paper's 2-D scorer, device block (ca_set_model_2d)
+    float *train2d = nullptr;     // its master weights [kC2Params], then momentum
+    float *partial2d = nullptr;   // its gradient partials [grad2d_grid][kC2GradStride]
+    int grad2d_grid = 0;
     int64_t strips_per_group = 0;   // 0: tuned per frame shape
     int cnn_groups_per_xcd = 0;     // resident learned-strip workgroups per XCD (0: not queried)
     std::map<std::array<int32_t, 4>, int32_t> tuned;   // (W, H, n_h, n_v) -> strip items per group

@@ -403,7 +403,8 @@ int ca_server_create(ca_ctx *ctx, const ca_server_config *cfg, ca_server **out)
     probe.pixel_stride = 3;
     if (cahost::validate(&probe, 1, cfg->params) != CA_OK)
         return CA_E_INVAL;
-    if (cfg->params.scorer == CA_SCORER_LEARNED && !ctx->model)
+    if ((cfg->params.scorer == CA_SCORER_LEARNED && !ctx->model)
+        || (cfg->params.scorer == CA_SCORER_LEARNED_2D && !ctx->model2d))
         return CA_E_INVAL;
     cahost::DeviceGuard guard(ctx->device);
     if (!guard.ok)

@@ -88,9 +88,38 @@ def frame_errors(specs, cx, cy, r, valid) -> np.ndarray:
     return np.asarray(out)
 
 
-def accuracy(est, frames_dev, specs, params, uids=None) -> dict:
+# border noise sigma buckets of the breakdown (the 1080p workloads draw
+# sigma in 2-8, the hard frames in 2-12)
+SIGMA_BUCKETS = ((0.0, 4.0), (4.0, 6.0), (6.0, 8.0), (8.0, 100.0))
+
+
+def breakdown(specs, errors, valid) -> dict:
+    """Share of frames within 2 px, median error, valid share and count per
+    frame kind and per border noise sigma bucket."""
+    from .synth import KIND_NAMES
+    e = np.asarray(errors, dtype=np.float64)
+    v = np.asarray(valid, dtype=bool)
+
+    def cell(sel):
+        sel = np.asarray(sel, dtype=bool)
+        if not sel.any():
+            return {"n": 0}
+        return {"n": int(sel.sum()), "frac_le_2px": float((e[sel] <= 2.0).mean()),
+                "median_px": float(np.median(e[sel])), "valid_frac": float(v[sel].mean())}
+
+    kinds = np.array([s.kind for s in specs])
+    sig = np.array([s.border_sigma for s in specs])
+    by_kind = {name: cell(kinds == k) for k, name in KIND_NAMES.items()}
+    by_sigma = {f"{lo:g}-{hi:g}" if hi < 100 else f">={lo:g}": cell((sig >= lo) & (sig < hi)
+                                                                    & (kinds != 2))
+                for lo, hi in SIGMA_BUCKETS}
+    return {"by_kind": by_kind, "by_border_sigma": by_sigma}
+
+
+def accuracy(est, frames_dev, specs, params, uids=None, by: bool = False) -> dict:
     """Run the estimator once on device frames and summarise its error
-    against the ground truth (plus the valid and fallback shares)."""
+    against the ground truth (plus the valid and fallback shares; with
+    `by`, the breakdown by frame kind and border noise)."""
     import torch
     B = len(specs)
     res = est.estimate_area(frames_dev, params, list(range(B)) if uids is None else uids)
@@ -102,5 +131,7 @@ def accuracy(est, frames_dev, specs, params, uids=None) -> dict:
     out = summarise(errs)
     out["valid_frac"] = float(valid.mean())
     out["fallback_frac"] = float((raw[:, 7] >= 256).mean())
+    if by:
+        out.update(breakdown(specs, errs, valid))
     return out
 

@@ -6,7 +6,9 @@ submission to the result being seen on the host, mean batch size, and the
 accuracy of the frames' own estimates and of the streams' filtered circles.
 
 Each scorer's server is fed in real time from its creation (no server fed a
-whole backlog at once runs before it in the process).
+whole backlog at once runs before it in the process).  Switched off (see
+OPEN_ISSUE): the serving latencies come from the serving test's real-time
+runs, which write them out when CA_SERVE_REPORT names a file.
 
     python -m paper_2210_14771_amd.serve_bench [--streams 48] [--seconds 0.4]
 """
@@ -80,7 +82,18 @@ def run_benchmark(n_streams: int = 48, seconds: float = 0.4, frames_per_stream: 
     return line
 
 
+OPEN_ISSUE = ("serve_bench is switched off: its real-time run stopped making progress on the GPU "
+              "in every run of this program, with or without a warm-up server before it, while "
+              "the serving tests' real-time runs pass; the cause is not found, so this program is "
+              "not run until it is")
+
+
 def main():
+    raise SystemExit(OPEN_ISSUE)
+
+
+def run_cli():
+    """The benchmark's command line (not run while OPEN_ISSUE stands)."""
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--streams", type=int, default=48)
     ap.add_argument("--seconds", type=float, default=0.4)

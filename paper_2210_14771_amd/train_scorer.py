@@ -13,6 +13,10 @@ the step runs on the host except drawing the frames' parameters.
 
 (the committed model: these defaults, 3125 steps of 64 frames = 200,000
 frames, 83 s on one MI355X; its log is models/scorer_1d_training.json).
+With --model 2d the same loop trains the paper's own network (three 3x3
+convolutions on RGBXY bands seven lines thick) through ca_cnn2d_gradients
+and ca_cnn2d_sgd_step, its input normaliser taken from the colour
+statistics of rendered training frames (models/scorer_2d.npy).
 """
 from __future__ import annotations
 
@@ -29,6 +33,10 @@ from . import api, synth, synth_gpu
 LAYERS = [(24, 16, 5), (16, 32, 5), (32, 32, 5), (32, 16, 5), (16, 1, 1)]
 MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
 MODEL_FILE = "scorer_1d.npy"
+# the paper's own network: three 3x3 convolutions 5 -> 8 -> 16 -> 32, 1x1 -> 1
+LAYERS_2D = [(5, 8, 9), (8, 16, 9), (16, 32, 9), (32, 1, 1)]
+MODEL_FILE_2D = "scorer_2d.npy"
+N_PARAMS_2D = 6215
 
 
 def init_params(seed: int, out_bias: float = -4.0) -> np.ndarray:
@@ -45,6 +53,23 @@ def init_params(seed: int, out_bias: float = -4.0) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def init_params_2d(seed: int, mean, std, out_bias: float = -4.0) -> np.ndarray:
+    """The 2-D network's model-file vector: the input normaliser (mean and
+    1 / std per colour channel), then weights and biases uniform in
+    +-1/sqrt(fan_in) (float32); the output bias starts at `out_bias`."""
+    rng = np.random.default_rng(seed)
+    parts = [np.asarray(mean, dtype=np.float32),
+             (1.0 / np.asarray(std, dtype=np.float64)).astype(np.float32)]
+    for ci, co, k in LAYERS_2D:
+        b = 1.0 / math.sqrt(ci * k)
+        parts.append(rng.uniform(-b, b, co * ci * k).astype(np.float32))
+        parts.append(rng.uniform(-b, b, co).astype(np.float32))
+    parts[-1][:] = out_bias
+    v = np.concatenate(parts)
+    assert v.size == N_PARAMS_2D
+    return v
+
+
 def load_model(path: str | None = None) -> np.ndarray:
     """The committed trained scorer (float32, model-file order)."""
     path = path or os.path.join(MODEL_DIR, MODEL_FILE)
@@ -52,6 +77,26 @@ def load_model(path: str | None = None) -> np.ndarray:
     if p.dtype != np.float32 or p.shape != (12273,):
         raise ValueError(f"{path}: not a scorer model")
     return p
+
+
+def load_model_2d(path: str | None = None) -> np.ndarray:
+    """The committed trained 2-D scorer (float32, model-file order)."""
+    path = path or os.path.join(MODEL_DIR, MODEL_FILE_2D)
+    p = np.load(path, allow_pickle=False)
+    if p.dtype != np.float32 or p.shape != (N_PARAMS_2D,):
+        raise ValueError(f"{path}: not a 2-D scorer model")
+    return p
+
+
+def colour_statistics(recs) -> tuple[np.ndarray, np.ndarray]:
+    """Per-channel mean and standard deviation of the pixels of rendered
+    training frames (the paper normalises by these over its training set)."""
+    import torch
+    frames = synth_gpu.DeviceRecipes(recs).render_frames()
+    x = frames.reshape(-1, 3).to(torch.float64)
+    mean = x.mean(dim=0)
+    std = x.std(dim=0)
+    return mean.cpu().numpy(), std.cpu().numpy()
 
 
 def draw_frames(stream_plain: int, stream_hard: int, first: int, n: int, hard_frac: float,
@@ -86,64 +131,94 @@ def positions_inside(desc: np.ndarray, recs) -> int:
     return int(np.maximum(hi - lo, 0).sum())
 
 
+def window_geometry(desc: np.ndarray, recs) -> np.ndarray:
+    """int32 [n, 8] (horizontal, line, start, width, height, 0, 0, 0) of the
+    windows of desc (frame, horizontal, line, start)."""
+    g = np.zeros((len(desc), 8), dtype=np.int32)
+    g[:, 0] = desc[:, 1]
+    g[:, 1] = desc[:, 2]
+    g[:, 2] = desc[:, 3]
+    g[:, 3] = [recs[f].spec.width for f in desc[:, 0]]
+    g[:, 4] = [recs[f].spec.height for f in desc[:, 0]]
+    return g
+
+
 class Batch:
-    def __init__(self, recs, desc, edge_boost):
+    def __init__(self, recs, desc, edge_boost, kind: str = "1d"):
+        import torch
         self.dev = synth_gpu.DeviceRecipes(recs)
         self.win, self.rng, self.tgt, self.wt = self.dev.render_windows(desc, edge_boost)
         self.scale = 1.0 / max(positions_inside(desc, recs), 1)
+        self.kind = kind
+        self.geom = (torch.from_numpy(window_geometry(desc, recs)).to(self.win.device)
+                     if kind == "2d" else None)
 
     def tensors(self):
+        if self.kind == "2d":
+            return self.win, self.geom, self.rng, self.tgt, self.wt
         return self.win, self.rng, self.tgt, self.wt
 
 
 def train(steps: int = 3125, frames_per_step: int = 64, strips_per_frame: int = 16,
           lr: float = 0.05, momentum: float = 0.9, warmup: int = 100, hard_frac: float = 0.5,
           edge_boost: float = 0.0, seed: int = 0, valid_every: int = 50, valid_frames: int = 128,
-          log=print, est: api.Estimator | None = None):
-    """Returns (best master weights, log dict)."""
+          log=print, est: api.Estimator | None = None, kind: str = "1d"):
+    """Returns (best master weights, log dict).  kind "1d": the 1-D strip
+    network; "2d": the paper's 3x3 network on RGBXY bands."""
     import torch
     own = est is None
     est = est or api.Estimator(0)
     rng = np.random.default_rng(seed)
-    est.set_model(init_params(seed))
+    info_extra = {}
+    if kind == "2d":
+        srng = np.random.default_rng(seed + 2)
+        mean, std = colour_statistics(draw_frames(synth_gpu.TRAIN_PLAIN, synth_gpu.TRAIN_HARD,
+                                                  10 ** 7, 32, hard_frac, srng))
+        info_extra = {"colour_mean": [float(v) for v in mean],
+                      "colour_std": [float(v) for v in std], "statistics_frames": 32}
+        est.set_model_2d(init_params_2d(seed, mean, std))
+        grads_of, sgd, get_model = est.cnn2d_gradients, est.cnn2d_sgd_step, est.get_model_2d
+    else:
+        est.set_model(init_params(seed))
+        grads_of, sgd, get_model = est.cnn_gradients, est.cnn_sgd_step, est.get_model
     vrng = np.random.default_rng(seed + 1)
     vrecs = draw_frames(synth_gpu.VALID_PLAIN, synth_gpu.VALID_HARD, 0, valid_frames, hard_frac,
                         vrng)
-    valid = Batch(vrecs, draw_windows(vrecs, strips_per_frame, vrng), edge_boost)
+    valid = Batch(vrecs, draw_windows(vrecs, strips_per_frame, vrng), edge_boost, kind)
     history = []
     best = (math.inf, None, -1)
     t0 = time.time()
     frames_seen = 0
     for step in range(steps + 1):
         if step % valid_every == 0 or step == steps:
-            _, vloss = est.cnn_gradients(*valid.tensors(), valid.scale)
+            _, vloss = grads_of(*valid.tensors(), valid.scale)
             v = float(vloss.item())
             history.append({"step": step, "valid_loss": v, "frames": frames_seen,
                             "seconds": round(time.time() - t0, 1)})
             log(f"step {step} valid loss {v:.5f} frames {frames_seen} "
                 f"({time.time() - t0:.0f} s)")
             if v < best[0]:
-                best = (v, est.get_model(), step)
+                best = (v, get_model(), step)
         if step == steps:
             break
         recs = draw_frames(synth_gpu.TRAIN_PLAIN, synth_gpu.TRAIN_HARD, step * frames_per_step,
                            frames_per_step, hard_frac, rng)
-        b = Batch(recs, draw_windows(recs, strips_per_frame, rng), edge_boost)
-        grad, loss = est.cnn_gradients(*b.tensors(), b.scale)
+        b = Batch(recs, draw_windows(recs, strips_per_frame, rng), edge_boost, kind)
+        grad, loss = grads_of(*b.tensors(), b.scale)
         if step < warmup:
             lr_t = lr * (step + 1) / warmup
         else:
             lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * (step - warmup) / max(steps - warmup, 1)))
-        est.cnn_sgd_step(grad, lr_t, momentum)
+        sgd(grad, lr_t, momentum)
         frames_seen += frames_per_step
         if step % 25 == 0:
             torch.cuda.synchronize()
     torch.cuda.synchronize()
-    info = {"steps": steps, "frames": frames_seen, "frames_per_step": frames_per_step,
+    info = {"model": kind, "steps": steps, "frames": frames_seen, "frames_per_step": frames_per_step,
             "strips_per_frame": strips_per_frame, "lr": lr, "momentum": momentum,
             "warmup": warmup, "hard_frac": hard_frac, "edge_boost": edge_boost, "seed": seed,
             "best_step": best[2], "best_valid_loss": best[0], "history": history,
-            "seconds": round(time.time() - t0, 1)}
+            "seconds": round(time.time() - t0, 1), **info_extra}
     if own:
         est.close()
     return best[1], info
@@ -161,14 +236,17 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--valid-every", type=int, default=50)
     ap.add_argument("--out", default=MODEL_DIR)
+    ap.add_argument("--model", choices=["1d", "2d"], default="1d",
+                    help="1d: the 1-D strip network; 2d: the paper's 3x3 network on RGBXY bands")
     a = ap.parse_args()
     params, info = train(a.steps, a.frames_per_step, a.strips_per_frame, a.lr, a.momentum,
                          hard_frac=a.hard_frac, edge_boost=a.edge_boost, seed=a.seed,
                          valid_every=a.valid_every,
-                         log=lambda s: print(s, flush=True))
+                         log=lambda s: print(s, flush=True), kind=a.model)
     os.makedirs(a.out, exist_ok=True)
-    np.save(os.path.join(a.out, MODEL_FILE), params.astype(np.float32), allow_pickle=False)
-    with open(os.path.join(a.out, "scorer_1d_training.json"), "w") as f:
+    name = MODEL_FILE if a.model == "1d" else MODEL_FILE_2D
+    np.save(os.path.join(a.out, name), params.astype(np.float32), allow_pickle=False)
+    with open(os.path.join(a.out, name.replace(".npy", "_training.json")), "w") as f:
         json.dump(info, f, indent=1)
     print(json.dumps({k: v for k, v in info.items() if k != "history"}), flush=True)
 

@@ -478,6 +478,31 @@ hipError_t launch_cnn_update(float *, float *, const float *, float, float, uint
 }
 hipError_t launch_cnn_pack(const float *, uint8_t *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mfma_probe(float *, hipStream_t) { return hipSuccess; }
+hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t)
+{
+    ++g_async_ops;
+    const int32_t S = a.n_h + a.n_v;
+    for (int32_t k = 0; k < a.n_items / S; ++k)
+        check_frame(a.frames, a.fd, a.strips, a.frame0 + k, a.n_h, a.n_v, 16384);
+    return hipSuccess;
+}
+hipError_t launch_cnn2d_windows(const uint8_t *, const uint8_t *, const int32_t *,
+                                const int32_t *, float *, int, hipStream_t)
+{
+    return hipSuccess;
+}
+hipError_t launch_cnn2d_grad(const Cnn2dTrainArgs &, int, hipStream_t) { return hipSuccess; }
+hipError_t launch_cnn2d_reduce(const float *, int, float *, float *, hipStream_t)
+{
+    return hipSuccess;
+}
+hipError_t launch_cnn2d_update(float *, float *, const float *, float, float, uint8_t *,
+                               hipStream_t)
+{
+    return hipSuccess;
+}
+hipError_t launch_cnn2d_pack(const float *, uint8_t *, hipStream_t) { return hipSuccess; }
+int cnn2d_grad_blocks_per_cu() { return 1; }
 hipError_t launch_cnn_windows(const uint8_t *, const uint8_t *, const int32_t *, float *, int,
                               hipStream_t)
 {

@@ -38,6 +38,14 @@ def test_learned_flops_per_frame():
     assert bench.cnn_flops_per_frame(1920, 1080, 32, 32) == 2.0 * macs * (32 * 1920 + 32 * 1080)
 
 
+def test_learned_2d_flops_per_frame():
+    # 9,896 multiply-adds per strip position: the band narrows by two lines
+    # per 3x3 layer (5, 3, 1 lines of 8, 16, 32 outputs), then the 1x1 layer
+    macs = 5 * 8 * 45 + 3 * 16 * 72 + 32 * 144 + 32
+    assert macs == 9_896
+    assert bench.cnn2d_flops_per_frame(1920, 1080, 32, 32) == 2.0 * macs * (32 * 1920 + 32 * 1080)
+
+
 def test_ransac_flops_counts_frames_with_three_points():
     # the method: one squared distance (5 flops) per attempt, point and pass
     assert bench.ransac_flops([0, 2], 1024, 3) == 0.0

@@ -47,3 +47,18 @@ def test_clipped_circle_edges():
 def test_summary():
     s = ev.summarise([1.0, 3.0, 20.0, 30.0])
     assert s["frac_le_2px"] == 0.25 and s["miss_pct"] == 50.0 and s["bad_miss_pct"] == 25.0
+
+
+def test_breakdown_by_kind_and_border_sigma():
+    from paper_2210_14771_amd import synth
+    specs = [synth.FrameSpec(1920, 1080, k, 960.0, 540.0, 500.0, s, 1.0, 0.0, 100.0)
+             for k, s in [(0, 3.0), (1, 5.0), (2, 7.0), (0, 9.0), (1, 4.0)]]
+    b = ev.breakdown(specs, [1.0, 3.0, 0.0, 1.5, 2.0], [1, 1, 0, 1, 1])
+    assert b["by_kind"]["partial"] == {"n": 2, "frac_le_2px": 1.0, "median_px": 1.25,
+                                       "valid_frac": 1.0}
+    assert b["by_kind"]["full"]["n"] == 2 and b["by_kind"]["full"]["frac_le_2px"] == 0.5
+    assert b["by_kind"]["noborder"]["valid_frac"] == 0.0
+    # border-free frames have no border noise: left out of the sigma buckets
+    sig = b["by_border_sigma"]
+    assert sig["0-4"]["n"] == 1 and sig["4-6"]["n"] == 2 and sig["6-8"] == {"n": 0}
+    assert sig[">=8"]["frac_le_2px"] == 1.0
