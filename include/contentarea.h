@@ -48,6 +48,7 @@ extern "C" {
 #define CA_E_UNSUPPORTED (-2)  /* layout the library does not handle (pixel_stride != 3) */
 #define CA_E_NOMEM (-3)        /* workspace budget of the context exceeded */
 #define CA_E_DEVICE (-4)       /* a HIP runtime call failed */
+#define CA_E_SCRATCH (-5)      /* batch larger than ca_estimate_area_noalloc's fixed scratch */
 
 #define CA_MAX_STRIPS 64       /* per direction */
 #define CA_MAX_ATTEMPTS 4096
@@ -161,6 +162,29 @@ void ca_destroy(ca_ctx *ctx);
 int ca_estimate_area(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
                      int32_t n_frames, const ca_params *params, ca_result *out_dev,
                      void *stream);
+
+/* ca_estimate_area without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * ca_estimate_area, computed by the same kernels.  Instead of the
+ * context's cached per-batch buffers, the call uses one fixed array in
+ * device memory of CA_NOALLOC_SCRATCH_BYTES per GPU, which the library
+ * holds until the process ends and which every call on that GPU shares
+ * (it keeps the last call's contents; each call rewrites what it reads).
+ * Calls that overlap on one GPU -- on two streams, or from two contexts --
+ * therefore race: serialise them (one stream per GPU).  The call uploads
+ * its descriptors and tables from host memory the library holds with one
+ * copy on `stream`, and waits on the host for the previous call's upload
+ * to have been read.  Limits: at most CA_NOALLOC_MAX_FRAMES frames of at
+ * most CA_NOALLOC_MAX_SHAPES distinct shapes, and the layout must fit the
+ * scratch (about 3.6 KB per frame at 64 + 64 strips and 4096 attempts);
+ * beyond them CA_E_SCRATCH, with nothing enqueued. */
+#define CA_NOALLOC_SCRATCH_BYTES (4u << 20)
+#define CA_NOALLOC_MAX_FRAMES 1024
+#define CA_NOALLOC_MAX_SHAPES 64
+int ca_estimate_area_noalloc(ca_ctx *ctx, const uint8_t *frames_dev,
+                             const ca_frame_desc *dims_host, int32_t n_frames,
+                             const ca_params *params, ca_result *out_dev, void *stream);
 
 /* The same pipeline, additionally writing every frame's P candidates
  * (Section 2.2.5, first sentence) to `points_dev` (n_frames * P entries). */

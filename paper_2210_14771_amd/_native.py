@@ -16,12 +16,17 @@ CA_E_INVAL = -1
 CA_E_UNSUPPORTED = -2
 CA_E_NOMEM = -3
 CA_E_DEVICE = -4
+CA_E_SCRATCH = -5
+CA_NOALLOC_SCRATCH_BYTES = 4 << 20
+CA_NOALLOC_MAX_FRAMES = 1024
+CA_NOALLOC_MAX_SHAPES = 64
 CA_MAX_STRIPS = 64
 CA_MAX_ATTEMPTS = 4096
 CA_MAX_EXTENT = 16384
 CA_SG_CAPACITY = 11541
 
 EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
+           "ca_estimate_area_noalloc",
            "ca_debug_candidates", "ca_debug_attempts", "ca_check_args", "ca_strip_positions",
            "ca_score_tables", "ca_profile_begin", "ca_profile_end", "ca_set_option",
            "ca_get_option", "ca_device_status", "ca_graph_create", "ca_graph_launch",
@@ -133,6 +138,7 @@ def lib() -> C.CDLL:
         L.ca_destroy.restype = None
         run_args = [vp, vp, C.POINTER(FrameDesc), i32, C.POINTER(Params)]
         L.ca_estimate_area.argtypes = run_args + [vp, vp]
+        L.ca_estimate_area_noalloc.argtypes = run_args + [vp, vp]
         L.ca_debug_candidates.argtypes = run_args + [vp, vp, vp]
         L.ca_debug_attempts.argtypes = run_args + [vp, vp, vp]
         L.ca_check_args.argtypes = [C.POINTER(FrameDesc), i32, C.POINTER(Params)]

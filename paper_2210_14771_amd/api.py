@@ -393,6 +393,20 @@ class Estimator:
         N.check(rc, "ca_estimate_area")
         return Result(out)
 
+    def estimate_area_noalloc(self, frames, params=None, frame_uids: Sequence[int] | None = None,
+                              out: torch.Tensor | None = None, stream=None) -> Result:
+        """estimate_area over the library's fixed device scratch instead of
+        allocated buffers (ca_estimate_area_noalloc); `out` is allocated here
+        only when not given."""
+        base, descs, n, p, s = self._prep(frames, params, frame_uids, stream)
+        if out is None:
+            out = torch.empty((n, 8), dtype=torch.int32, device=self.device)
+        rc = N.lib().ca_estimate_area_noalloc(self._ctx, C.c_void_p(base), descs, n, C.byref(p),
+                                              C.c_void_p(out.data_ptr()),
+                                              C.c_void_p(s.cuda_stream))
+        N.check(rc, "ca_estimate_area_noalloc")
+        return Result(out)
+
     def autotune(self, frames, params=None, frame_uids=None, reps: int = 5) -> dict:
         """Tune the strip tile (strip items per workgroup) of every frame shape
         in the batch; returns {(width, height): T}."""

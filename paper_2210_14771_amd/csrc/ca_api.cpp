@@ -645,6 +645,9 @@ int ca_create(ca_ctx **out, int device, size_t budget)
             ok = hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking) == hipSuccess
                  && hipEventCreateWithFlags(&c->join[k], hipEventDisableTiming) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
+        // the device address of the no-allocation entry point's scratch on
+        // this device (a failure only disables that entry point)
+        (void)scratch_setup(device);
         if (!ok) {
             (void)hipGetLastError();
             ca_destroy(c);
@@ -1417,6 +1420,9 @@ const char *ca_error_string(int code)
         return "workspace budget exceeded or out of memory";
     case CA_E_DEVICE:
         return "HIP runtime error";
+    case CA_E_SCRATCH:
+        return "batch exceeds the fixed scratch of ca_estimate_area_noalloc (frames, frame "
+               "shapes or bytes)";
     default:
         return "unknown error";
     }

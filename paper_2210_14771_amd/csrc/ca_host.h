@@ -147,6 +147,9 @@ int plan_layout(const ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const c
 void plan_pointers(Plan *pl, void *base, const PlanLayout &L);
 // Resident workgroups of the fused kernel for this LDS size.
 int fused_grid(const ca_ctx *ctx, size_t fused_lds);
+// Once per device with the device current: locate the no-allocation entry
+// point's scratch (ca_noalloc.hip).
+int scratch_setup(int device);
 int build_plan(ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const ca_params &p, Plan **out);
 void free_plan(ca_ctx *ctx, Plan *pl);
 // Enqueue the whole path for frames [0, n) of a plan on stream s.
