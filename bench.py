@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=0.4,
                     help="seconds of simulated arrivals of the 48-stream serving loop, plain "
                          "and learned side by side, in a child process (0: skip)")
+    ap.add_argument("--small-only", action="store_true",
+                    help="run only the small case (8 x 640x480) and print its JSON (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -484,6 +486,10 @@ def main():
     from concurrent.futures import ThreadPoolExecutor
 
     from paper_2210_14771_amd import api, evaluate, synth
+
+    if args.small_only:
+        print(json.dumps(small_section(args)), flush=True)
+        return
 
     wl = synth.HD_1080p
     B, W, H = wl.n_frames, wl.width, wl.height

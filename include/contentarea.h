@@ -383,6 +383,11 @@ void ca_graph_destroy(ca_graph *graph);
 #define CA_OPT_STRIPS_PER_GROUP 7  /* split: strip items per workgroup tile, 1..16, for
                                       every frame shape; 0 (default) = the autotuned value
                                       of each shape (ca_autotune), else 1 */
+#define CA_OPT_RANSAC_LANES 8  /* split: lanes per RANSAC attempt, 2, 4, 8 or 16 (a
+                                  workgroup takes 256 / lanes attempts); 0 (default) = the
+                                  fewest lanes that give the batch at least one attempt
+                                  workgroup per compute unit, at most 16.  Results do
+                                  not depend on it. */
 #define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from

@@ -53,6 +53,7 @@ CA_OPT_GRID = 4
 CA_OPT_SPIN_LIMIT = 5
 CA_OPT_PIPELINE = 6
 CA_OPT_STRIPS_PER_GROUP = 7
+CA_OPT_RANSAC_LANES = 8
 CA_SCHEDULE_SPLIT = 0
 CA_SCHEDULE_FUSED = 1
 CA_SCHEDULE_AUTO = 2

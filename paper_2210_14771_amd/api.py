@@ -184,7 +184,8 @@ class Estimator:
 
     OPTIONS = {"schedule": N.CA_OPT_SCHEDULE, "lag": N.CA_OPT_LAG, "queues": N.CA_OPT_QUEUES,
                "grid": N.CA_OPT_GRID, "spin_limit": N.CA_OPT_SPIN_LIMIT,
-               "pipeline": N.CA_OPT_PIPELINE, "strips_per_group": N.CA_OPT_STRIPS_PER_GROUP}
+               "pipeline": N.CA_OPT_PIPELINE, "strips_per_group": N.CA_OPT_STRIPS_PER_GROUP,
+               "ransac_lanes": N.CA_OPT_RANSAC_LANES}
 
     def set_option(self, name: str, value: int) -> None:
         """Options: schedule ("split"/"fused"/"auto" or 0/1/2), pipeline (sub-batches of a split

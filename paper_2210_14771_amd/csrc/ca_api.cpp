@@ -154,7 +154,8 @@ int plan_layout(const ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const c
     pl->t_theta = p.t_theta_deg;
     pl->t_iota = p.t_iota;
     pl->P = 2 * S;
-    pl->groups = (p.ransac_attempts + ca::kAttemptsPerGroup - 1) / ca::kAttemptsPerGroup;
+    pl->groups = ca::attempt_groups(p.ransac_attempts, ca::kLanesPerAttempt);
+    pl->rec_groups = ca::attempt_groups(p.ransac_attempts, ca::kMaxLanesPerAttempt);
     pl->sg_len = sg_len;
     // distinct frame shapes in order of first appearance
     int32_t n_shapes = 0, longest = 0;
@@ -188,7 +189,7 @@ int plan_layout(const ca_ctx *ctx, const ca_frame_desc *dims, int32_t n, const c
     L->image_bytes = L->o_ctl + sizeof(uint32_t) * ca::ctl_words(n);
     L->o_cand = align_up(L->image_bytes, 256);
     L->o_rec = align_up(L->o_cand + sizeof(ca_point) * (size_t)n * (size_t)pl->P, 256);
-    L->o_res2 = align_up(L->o_rec + sizeof(Record) * (size_t)n * (size_t)pl->groups, 256);
+    L->o_res2 = align_up(L->o_rec + sizeof(Record) * (size_t)n * (size_t)pl->rec_groups, 256);
     L->total = align_up(L->o_res2 + sizeof(ca_result) * (size_t)n, 256);
     if (!image)
         return CA_OK;
@@ -353,10 +354,36 @@ hipError_t launch_class_strips(const ca::StripArgs &base, const Plan *pl,
     return ca::launch_strips(a, pl->lds, st);
 }
 
+// Lanes per RANSAC attempt of an n-frame split call: the fewest that give
+// at least one attempt workgroup per compute unit (a small batch otherwise
+// leaves most of the device idle), at most 8 (measured on 8 x 640x480 with
+// 256 attempts: 16.5, 14.4, 13.5 and 15.4 us per launch at 2, 4, 8 and 16
+// lanes; beyond 8 the per-attempt solves repeated on every lane cost more
+// than the shorter point loops save).
+int32_t ransac_lanes(const ca_ctx *ctx, int32_t n, int32_t attempts)
+{
+    if (ctx->ransac_lanes > 0)
+        return (int32_t)ctx->ransac_lanes;
+    constexpr int32_t kAutoMaxLanes = 8;
+    int32_t lanes = ca::kLanesPerAttempt;
+    while (lanes < kAutoMaxLanes
+           && (int64_t)n * ca::attempt_groups(attempts, lanes) < (int64_t)ctx->n_cu)
+        lanes *= 2;
+    return lanes;
+}
+
 int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
                 ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
                 bool timed)
 {
+    const bool fused = ctx->schedule == CA_SCHEDULE_FUSED
+                       || (ctx->schedule == CA_SCHEDULE_AUTO
+                           && pl->tuned_schedule == CA_SCHEDULE_FUSED);
+    const bool fused_path = fused && p.scorer == CA_SCORER_HANDCRAFTED;
+    // the persistent kernel takes attempt groups of two lanes per attempt
+    const int32_t lanes =
+        fused_path ? ca::kLanesPerAttempt : ransac_lanes(ctx, n, p.ransac_attempts);
+    const int32_t groups = ca::attempt_groups(p.ransac_attempts, lanes);
 
     ca::StripArgs sa;
     sa.frames = frames;
@@ -391,7 +418,8 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     ra.attempts = p.ransac_attempts;
     ra.refine = p.refine_iters;
     ra.sampler = p.sampler;
-    ra.groups = pl->groups;
+    ra.groups = groups;
+    ra.lanes = lanes;
     ra.frame0 = 0;
     ra.groups_done = pl->ctl + ca::kCtlFrames + n;
 
@@ -400,16 +428,13 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     se.out = out;
     se.threshold = p.t_cs * 16777216.0 * (double)pl->P;
     se.P = pl->P;
-    se.groups = pl->groups;
+    se.groups = groups;
     se.n_frames = n;
 
     hipEvent_t *ev = nullptr;
     if (timed && ctx->prof_used < ctx->prof_capacity)
         ev = &ctx->prof_events[4 * (size_t)ctx->prof_used++];
-    const bool fused = ctx->schedule == CA_SCHEDULE_FUSED
-                       || (ctx->schedule == CA_SCHEDULE_AUTO
-                           && pl->tuned_schedule == CA_SCHEDULE_FUSED);
-    if (fused && p.scorer == CA_SCORER_HANDCRAFTED) {
+    if (fused_path) {
         ca::FusedArgs fa;
         fa.s = sa;
         fa.r = ra;
@@ -1314,6 +1339,11 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
             return CA_E_INVAL;
         ctx->strips_per_group = value;
         return CA_OK;
+    case CA_OPT_RANSAC_LANES:
+        if (value != 0 && value != 2 && value != 4 && value != 8 && value != 16)
+            return CA_E_INVAL;
+        ctx->ransac_lanes = value;
+        return CA_OK;
     default:
         return CA_E_INVAL;
     }
@@ -1344,6 +1374,9 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value)
         return CA_OK;
     case CA_OPT_STRIPS_PER_GROUP:
         *value = ctx->strips_per_group;
+        return CA_OK;
+    case CA_OPT_RANSAC_LANES:
+        *value = ctx->ransac_lanes;
         return CA_OK;
     default:
         return CA_E_INVAL;

@@ -45,6 +45,7 @@ struct Plan {
     int32_t tuned_schedule = -1; // faster schedule of this batch (ca_autotune), -1 untuned
     // launch facts
     int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
+    int32_t rec_groups = 0;     // attempt-group records per frame the block holds (16 lanes)
     bool rows_aligned = false;  // every row offset a multiple of 16
     size_t lds = 0;
     size_t fused_lds = 0;
@@ -105,6 +106,7 @@ struct ca_ctx {
     float *partial2d = nullptr;   // its gradient partials [grad2d_grid][kC2GradStride]
     int grad2d_grid = 0;
     int64_t strips_per_group = 0;   // 0: tuned per frame shape
+    int64_t ransac_lanes = 0;       // 0: chosen per batch from its attempt workgroups
     int cnn_groups_per_xcd = 0;     // resident learned-strip workgroups per XCD (0: not queried)
     std::map<std::array<int32_t, 4>, int32_t> tuned;   // (W, H, n_h, n_v) -> strip items per group
     // score tables of the last (t_g, t_theta, t_iota): SG[lut_sg_len] | ST | SI

@@ -11,8 +11,11 @@ namespace ca {
 
 constexpr int kBlock = 256;      // threads per workgroup of every kernel
 constexpr int kHalfThreads = 128; // threads per half strip
-constexpr int kLanesPerAttempt = 2;                        // lanes sharing one RANSAC attempt
-constexpr int kAttemptsPerGroup = kBlock / kLanesPerAttempt; // attempts per RANSAC workgroup
+constexpr int kLanesPerAttempt = 2;   // lanes sharing one RANSAC attempt (fused schedule, and
+                                      // the split schedule when a batch fills the device)
+constexpr int kMaxLanesPerAttempt = 16;  // small batches spread attempts over more workgroups
+// Attempt groups (workgroups) per frame with `lanes` lanes per attempt.
+inline int attempt_groups(int attempts, int lanes) { return (attempts * lanes + kBlock - 1) / kBlock; }
 constexpr int kChunk = 8;        // most pixels one thread scores per pass (a 1920-pixel line in one pass)
 constexpr int kQtBins = 2049;    // pseudo-angle bins, 0 .. 2048
 constexpr int kLumaLevels = 256;
@@ -65,7 +68,8 @@ struct RansacArgs {
     int32_t attempts;
     int32_t refine;
     int32_t sampler;
-    int32_t groups;         // attempt groups (of kAttemptsPerGroup) per frame
+    int32_t groups;         // attempt groups (workgroups of kBlock / lanes attempts) per frame
+    int32_t lanes;          // lanes per attempt: 2, 4, 8 or 16
     int32_t frame0;         // first frame of this launch (blockIdx.y counts from it)
     uint32_t *groups_done;  // per frame: groups finished (the last one selects), or null
 };

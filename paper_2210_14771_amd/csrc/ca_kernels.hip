@@ -66,6 +66,17 @@ __device__ __forceinline__ void store_dev(uint32_t *p, uint32_t v)
 // write back the whole L2 of the XCD (buffer_wbl2), which costs more than
 // the strip itself.  The writer waits for its stores to complete before the
 // workgroup barrier; only then does one thread move the counter.
+//
+// This relies on the hardware, not on the HIP memory model: the counter
+// update is relaxed, not a release, and the reader's loads are relaxed, not
+// acquires.  What makes it sound on gfx950: device-scope stores complete at
+// the coherence point before s_waitcnt returns, the counter's atomic is
+// performed there after them (program order across the barrier), and
+// device-scope loads bypass the non-coherent caches, so a reader that sees
+// the counter's new value and then loads the data gets what was stored.  A
+// compiler or target that reordered relaxed device-scope accesses across the
+// wait, or cached them, would break it; the repeated-call and graph-replay
+// tests compare every result against the split schedule.
 __device__ __forceinline__ void wait_memory() { __builtin_amdgcn_s_waitcnt(0); }
 __device__ __forceinline__ uint32_t add_dev(uint32_t *p, uint32_t v)
 {
@@ -478,14 +489,17 @@ __device__ __forceinline__ double quad_xor(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+template <int LANES>
 __device__ __forceinline__ double lane_sum(double v)
 {
-    static_assert(kLanesPerAttempt == 1 || kLanesPerAttempt == 2 || kLanesPerAttempt == 4,
-                  "attempt lanes");
-    if (kLanesPerAttempt >= 2)
-        v += quad_xor<0xB1>(v);  // quad_perm [1, 0, 3, 2]
-    if (kLanesPerAttempt >= 4)
+    static_assert(LANES == 2 || LANES == 4 || LANES == 8 || LANES == 16, "attempt lanes");
+    v += quad_xor<0xB1>(v);  // quad_perm [1, 0, 3, 2]
+    if (LANES >= 4)
         v += quad_xor<0x4E>(v);  // quad_perm [2, 3, 0, 1]
+    if (LANES >= 8)
+        v += __shfl_xor(v, 4, 64);
+    if (LANES >= 16)
+        v += __shfl_xor(v, 8, 64);
     return v;
 }
 
@@ -502,13 +516,14 @@ struct Moments {
     double m, su, sv, suu, suv, svv, suz, svz;
 };
 
-// Lane `sub` of the attempt takes points sub, sub + kLanesPerAttempt, ...;
-// nk = padded point count / kLanesPerAttempt (wave-uniform).
+// Lane `sub` of the attempt takes points sub, sub + LANES, ...;
+// nk = padded point count / LANES (wave-uniform).
+template <int LANES>
 __device__ Moments band_moments(const Lds &L, int nk, int sub, const Band &b)
 {
     Moments s = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < nk; ++k) {
-        const int i = k * kLanesPerAttempt + sub;
+        const int i = k * LANES + sub;
         const double2 p = L.uv[i];
         const double w = in_band(p, b);
         const double2 m1 = L.m1[i], m2 = L.m2[i], m3 = L.m3[i];
@@ -521,14 +536,14 @@ __device__ Moments band_moments(const Lds &L, int nk, int sub, const Band &b)
         s.suz = fma(w, m3.x, s.suz);
         s.svz = fma(w, m3.y, s.svz);
     }
-    s.m = lane_sum(s.m);
-    s.su = lane_sum(s.su);
-    s.sv = lane_sum(s.sv);
-    s.suu = lane_sum(s.suu);
-    s.suv = lane_sum(s.suv);
-    s.svv = lane_sum(s.svv);
-    s.suz = lane_sum(s.suz);
-    s.svz = lane_sum(s.svz);
+    s.m = lane_sum<LANES>(s.m);
+    s.su = lane_sum<LANES>(s.su);
+    s.sv = lane_sum<LANES>(s.sv);
+    s.suu = lane_sum<LANES>(s.suu);
+    s.suv = lane_sum<LANES>(s.suv);
+    s.svv = lane_sum<LANES>(s.svv);
+    s.suz = lane_sum<LANES>(s.suz);
+    s.svz = lane_sum<LANES>(s.svz);
     return s;
 }
 
@@ -578,7 +593,7 @@ __device__ bool coope_solve(const Moments &s, double &cx, double &cy, double &r2
 // inlier passes with least-squares refits, then count the inliers and their
 // score sum and apply the circle limits.  `key` is set for kept circles (on
 // the attempt's first lane).
-template <bool kExact>
+template <bool kExact, int LANES>
 __device__ void run_attempt(const RansacArgs &a, const Lds &L, const FrameDev &d, int n, int nk,
                             int sub, int att, bool active, ca_attempt &rec, uint64_t &key)
 {
@@ -607,7 +622,7 @@ __device__ void run_attempt(const RansacArgs &a, const Lds &L, const FrameDev &d
                 r2 = ddx * ddx + ddy * ddy;
                 for (int k = 1; k <= a.refine; ++k) {
                     const Band bd = make_band(cx, cy, r2, a.t_ri);
-                    if (!coope_solve<kExact>(band_moments(L, nk, sub, bd), cx, cy, r2)) {
+                    if (!coope_solve<kExact>(band_moments<LANES>(L, nk, sub, bd), cx, cy, r2)) {
                         rec.fail_stage = k;
                         ok = false;
                         break;
@@ -618,13 +633,13 @@ __device__ void run_attempt(const RansacArgs &a, const Lds &L, const FrameDev &d
                 const Band bd = make_band(cx, cy, r2, a.t_ri);
                 double cnt = 0, qs = 0;
                 for (int k = 0; k < nk; ++k) {
-                    const int i = k * kLanesPerAttempt + sub;
+                    const int i = k * LANES + sub;
                     const double w = in_band(L.uv[i], bd);
                     cnt += w;
                     qs = fma(w, L.m2[i].y, qs);
                 }
-                cnt = lane_sum(cnt);
-                qs = lane_sum(qs);
+                cnt = lane_sum<LANES>(cnt);
+                qs = lane_sum<LANES>(qs);
                 const double acx = (double)ox + cx;
                 const double acy = (double)oy + cy;
                 const double r = sqrt(r2);
@@ -646,9 +661,10 @@ __device__ void run_attempt(const RansacArgs &a, const Lds &L, const FrameDev &d
     }
 }
 
-// One RANSAC item: attempts [g * A, g * A + A) of frame f (A =
-// kAttemptsPerGroup), kLanesPerAttempt lanes per attempt.  Writes the group's
-// best attempt to its record (device scope) and ends with a barrier.
+// One RANSAC item: attempts [g * A, g * A + A) of frame f (A = kBlock /
+// LANES), LANES lanes per attempt.  Writes the group's best attempt to its
+// record (device scope) and ends with a barrier.
+template <int LANES>
 __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
 {
     const int tid = threadIdx.x;
@@ -682,7 +698,7 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
     for (int w = 0; w < wv; ++w)
         base += L.wcount[w];
     const int n = uniform(L.wcount[0] + L.wcount[1] + L.wcount[2] + L.wcount[3]);
-    const int nk = (n + kLanesPerAttempt - 1) / kLanesPerAttempt;
+    const int nk = (n + LANES - 1) / LANES;
     if (keep) {
         const int j = base + before;
         const int u = x - ox, v = y - oy;
@@ -695,7 +711,7 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
         L.m2[j] = make_double2((double)((int64_t)v * v), (double)(uint32_t)(sc * 16777216.0f));
         L.m3[j] = make_double2(du * z, dv * z);
     }
-    if (tid >= n && tid < nk * kLanesPerAttempt) {
+    if (tid >= n && tid < nk * LANES) {
         // padding: squared distance ~1e300 exceeds every band's outer radius
         L.uv[tid] = make_double2(1e150, 1e150);
         L.m1[tid] = make_double2(0.0, 0.0);
@@ -710,15 +726,15 @@ __device__ void ransac_work(const RansacArgs &a, Lds &L, int f, int g)
     const bool exact =
         uniform((double)n * (double)n * (U > V ? U : V) * (U * U + V * V) < 0x1p52 ? 1 : 0) != 0;
 
-    const int sub = tid & (kLanesPerAttempt - 1);
-    const int att = g * kAttemptsPerGroup + tid / kLanesPerAttempt;
+    const int sub = tid & (LANES - 1);
+    const int att = g * (kBlock / LANES) + tid / LANES;
     const bool active = att < a.attempts;
     uint64_t key = 0;
     ca_attempt rec = {};
     if (exact)
-        run_attempt<true>(a, L, d, n, nk, sub, att, active, rec, key);
+        run_attempt<true, LANES>(a, L, d, n, nk, sub, att, active, rec, key);
     else
-        run_attempt<false>(a, L, d, n, nk, sub, att, active, rec, key);
+        run_attempt<false, LANES>(a, L, d, n, nk, sub, att, active, rec, key);
     if (a.dbg && active && sub == 0)
         a.dbg[(int64_t)f * a.attempts + att] = rec;
 
@@ -836,12 +852,13 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
 
 // RANSAC groups of frames frame0 .. frame0 + gridDim.y - 1; the last group
 // of a frame to finish selects its circle and rearms the frame's counter.
+template <int LANES>
 __global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a, SelectArgs sel)
 {
     __shared__ Lds L;
     __shared__ int s_last;
     const int f = a.frame0 + (int)blockIdx.y;
-    ransac_work(a, L, f, blockIdx.x);
+    ransac_work<LANES>(a, L, f, blockIdx.x);
     if (threadIdx.x == 0)
         s_last = add_dev(a.groups_done + f, 1u) == (uint32_t)(a.groups - 1);
     __syncthreads();
@@ -954,7 +971,7 @@ __global__ __launch_bounds__(kBlock) void k_fused(FusedArgs a)
                 }
             }
             __syncthreads();
-            ransac_work(a.r, L, tk.f, tk.idx);
+            ransac_work<kLanesPerAttempt>(a.r, L, tk.f, tk.idx);
             if (tid == 0)
                 s_last = add_dev(groups_done + tk.f, 1u) == (uint32_t)(G - 1);
             __syncthreads();
@@ -1045,7 +1062,22 @@ hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frame
 {
     if (n_frames <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_ransac, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+    switch (a.lanes) {
+    case 2:
+        hipLaunchKernelGGL(k_ransac<2>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_ransac<4>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        break;
+    case 8:
+        hipLaunchKernelGGL(k_ransac<8>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        break;
+    case 16:
+        hipLaunchKernelGGL(k_ransac<16>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -199,3 +199,86 @@ def test_sgd_step_updates_master_and_model(torch_dev, est):
         ref = cnn2d.window_forward(win[i], geom[i], int(ranges[i, 0]), int(ranges[i, 1]), new)
         ok = ~np.isnan(ref)
         assert np.abs(z[i][ok] - ref[ok]).max() <= LOGIT_TOL
+
+
+def test_trained_2d_scorer_1080p_candidates_ransac_and_fallback(torch_dev):
+    """The committed trained 2-D network on two headline 1080p frames with
+    32+32 strips: every candidate is a within-tolerance maximum of the
+    oracle's half-strip scores; the RANSAC over the kept candidates equals the
+    oracle's attempt by attempt; with the 0.5 inlier fallback a frame below
+    the fraction carries the oracle's handcrafted result."""
+    import os
+
+    import oracle
+    from paper_2210_14771_amd import train_scorer
+
+    from gpu_helpers import assert_attempts_equal, assert_results_equal, oracle_params
+
+    torch = torch_dev
+    path = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE_2D)
+    if not os.path.exists(path):
+        pytest.skip("no trained 2-D scorer model")
+    flat = train_scorer.load_model_2d(path)
+    params = cnn2d.unflat_params(flat.astype(np.float64))
+    e = api.Estimator(0)
+    e.set_model_2d(flat)
+    frames, _ = synth.make_batch(synth.HD_1080p, 2)
+    dev = torch.from_numpy(frames).cuda()
+    uids = [0, 1]
+    kw = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+    say("trained 2-D scorer at 1080p")
+    _, pts = e.debug_candidates(dev, api.default_params(**kw, scorer=2), uids)
+    res_l, att = e.debug_attempts(dev, api.default_params(**kw, scorer=2), uids)
+    res_f = e.estimate_area(dev, api.default_params(**kw, scorer=2, fallback_inlier_frac=0.5),
+                            uids)
+    torch.cuda.synchronize()
+    g = api.points_numpy(pts)
+    res_l, res_f = res_l.numpy(), res_f.numpy()
+    att = api.attempts_numpy(att)
+    op = oracle_params(**kw)
+    for f in range(2):
+        halves = cnn2d.learned_half_strip_scores(frames[f], params, 32, 32)
+        for c, (xs, ys, sc) in enumerate(halves):
+            gx, gy, gs = int(g[f][c]["x"]), int(g[f][c]["y"]), float(g[f][c]["score"])
+            idx = np.flatnonzero((xs == gx) & (ys == gy))
+            assert idx.size == 1, (f, c, gx, gy)
+            assert sc[idx[0]] >= sc.max() - 0.01, (f, c, sc[idx[0]], sc.max())
+            assert abs(gs - sc[idx[0]]) <= 0.01
+        s32 = g[f]["score"].astype(np.float32)
+        keep = s32 >= np.float32(op.t_ps)
+        xs = g[f]["x"][keep].astype(np.int32)
+        ys = g[f]["y"][keep].astype(np.int32)
+        sq = (s32[keep].astype(np.float64) * 2.0 ** 24).astype(np.uint32)
+        assert int(res_l[f]["n_points"]) == int(keep.sum())
+        assert_attempts_equal([att[f]], [oracle.ransac_attempts(xs, ys, sq, 1920, 1080, uids[f], op)])
+        n = int(res_l[f]["n_points"])
+        if n < 3 or np.float32(res_l[f]["inliers"]) < np.float32(0.5) * np.float32(n):
+            want = oracle.estimate(frames[f], op, uids[f]).copy()
+            want["reason"] += 256
+            assert_results_equal([res_f[f]], [want])
+        else:
+            assert res_f[f].tobytes() == res_l[f].tobytes()
+    e.close()
+
+
+def test_trained_2d_scorer_gains_on_hard_frames(torch_dev):
+    """The paper's own network, trained here, against the handcrafted scorer
+    on device-rendered hard frames (low-contrast rims, strong border noise,
+    specular blobs, text in the border)."""
+    import os
+
+    from paper_2210_14771_amd import evaluate, synth_gpu, train_scorer
+
+    path = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE_2D)
+    if not os.path.exists(path):
+        pytest.skip("no trained 2-D scorer model")
+    e = api.Estimator(0)
+    e.set_model_2d(train_scorer.load_model_2d(path))
+    frames, specs = synth_gpu.render_set(synth.HARD_1080p, synth.HARD_1080p.config_id, 64, True)
+    kw = dict(n_hstrips=32, n_vstrips=32, ransac_attempts=1024)
+    plain = evaluate.accuracy(e, frames, specs, api.default_params(**kw))
+    learned = evaluate.accuracy(e, frames, specs, api.default_params(**kw, scorer=2))
+    say(f"hard frames: plain {plain}  2-D learned {learned}")
+    assert learned["frac_le_2px"] >= plain["frac_le_2px"] + 0.2
+    assert learned["median_px"] < plain["median_px"]
+    e.close()

@@ -86,6 +86,22 @@ def test_hd_workload_parity(torch_dev, est, hd_batch):
     assert bits[0] == bits[1]
 
 
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+def test_ransac_lanes_per_attempt(torch_dev, small_batch, lanes):
+    # the attempts of a small batch spread over more workgroups (more lanes
+    # share an attempt's inlier passes): every attempt, candidate and result
+    # still equals the oracle
+    e = api.Estimator(0)
+    e.set_option("schedule", "split")
+    e.set_option("ransac_lanes", lanes)
+    frames, _ = small_batch
+    say(f"ransac lanes {lanes}")
+    g, r, bits = _full_parity(torch_dev, e, frames, SMALL)
+    assert bits[0] == bits[1]
+    e.device_status()
+    e.close()
+
+
 WIDE = dict(n_hstrips=64, n_vstrips=64, ransac_attempts=256, t_ps=0.0, t_px=0)
 
 
