@@ -386,7 +386,7 @@ void ca_graph_destroy(ca_graph *graph);
 #define CA_OPT_RANSAC_LANES 8  /* split: lanes per RANSAC attempt, 2, 4, 8 or 16 (a
                                   workgroup takes 256 / lanes attempts); 0 (default) = the
                                   fewest lanes that give the batch at least one attempt
-                                  workgroup per compute unit, at most 16.  Results do
+                                  workgroup per compute unit, at most 8.  Results do
                                   not depend on it. */
 #define CA_SCHEDULE_SPLIT 0    /* per (sub-)batch two launches: strip scoring, then RANSAC
                                   whose last group per frame selects the circle */

@@ -33,6 +33,8 @@ constexpr int kC2Halo = 3;         // the network's receptive-field radius
 constexpr int kC2Stride = kC2Win - 2 * kC2Halo;   // exact logits per strip window
 constexpr int kTrainHalo = 8;      // training windows carry logits 8 .. 119
 constexpr int kTrainOut = kC2Win - 2 * kTrainHalo;
+constexpr int kC2Floats = 96;      // floats of the model's float block
+constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
@@ -45,6 +47,7 @@ struct alignas(16) FwdLds {
     __bf16 h2[3 * kPos * 16];
     __bf16 h3[kPos * 32];
     float z[kC2Win];
+    float fb[kC2Floats];   // the model's float block (biases, w4, b4, colour statistics)
 };
 
 // The backward pass adds the signals at the pre-activations (ReLU and masks
@@ -67,27 +70,55 @@ __device__ void clear(__bf16 *p, int n)
         p[i] = to_bf16(0.0f);
 }
 
+// The A operand of a layer's GEMMs (weights [M][KP], M = 16 MT output
+// channels) as this lane's MFMA fragments: loaded once, kept in registers
+// for every tile of every window the workgroup computes.
+template <int KP, int MT>
+struct Frag {
+    bf16x8 a[MT][KP / 32];
+};
+
+template <int KP, int MT>
+__device__ __forceinline__ Frag<KP, MT> load_frag(const __bf16 *A)
+{
+    const int lane = threadIdx.x & 63;
+    Frag<KP, MT> f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KP / 32; ++ks)
+            f.a[mt][ks] = *reinterpret_cast<const bf16x8 *>(A + (mt * 16 + (lane & 15)) * KP
+                                                            + 32 * ks + 8 * (lane >> 4));
+    return f;
+}
+
 // One 3x3 convolution layer over a window as GEMMs, one per output line i:
 // acc[m][n] = sum_k A[m][k] B_i[k][n] with B_i[(3 da + dl) CP + c][n] =
 // X[line i + da][n + dl - 1][c] (lines outside [x_lo, x_hi) read the zero
-// line); epi(i, m0, n, acc) receives rows m0 .. m0 + 3 of column n.
+// line).  A wave takes position tiles (16 positions of one output line) and
+// computes all MT channel tiles of each from one read of its B fragments;
+// epi(i, m0, n, acc) receives rows m0 .. m0 + 3 of column n.
 template <int CP, int KP, int MT, int OUT_LINES, class Epi>
-__device__ void gemm3x3(const __bf16 *A, const __bf16 *X, int x_lo, int x_hi, const __bf16 *zero,
-                        Epi epi)
+__device__ __forceinline__ void gemm3x3(const Frag<KP, MT> &F, const __bf16 *X, int x_lo,
+                                        int x_hi, const __bf16 *zero, Epi epi)
 {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     constexpr int NT = kC2Win / 16;
     constexpr int CB = CP / 8;
     constexpr int G = 9 * CB;   // real 8-wide K groups; the rest have zero weights
+    static_assert((OUT_LINES * NT) % kWaves == 0, "tiles must split evenly over the waves");
     const int kq = lane >> 4;
-    for (int tile = wv; tile < OUT_LINES * NT * MT; tile += kBlock / 64) {
-        const int mt = tile % MT;
-        const int nt = (tile / MT) % NT;
-        const int i = tile / (MT * NT);
-        const int m = mt * 16 + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < OUT_LINES * NT / kWaves; ++t) {
+        const int tile = wv + kWaves * t;
+        const int nt = tile % NT;
+        const int i = tile / NT;
         const int n = nt * 16 + (lane & 15);
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        f32x4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int ks = 0; ks < KP / 32; ++ks) {
             int g = 4 * ks + kq;
@@ -96,12 +127,51 @@ __device__ void gemm3x3(const __bf16 *A, const __bf16 *X, int x_lo, int x_hi, co
             const int da = tap / 3, dl = tap - 3 * (tap / 3);
             const int line = i + da;
             const __bf16 *src = (line >= x_lo && line < x_hi) ? X + (line - x_lo) * kPos * CP : zero;
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + m * KP + 32 * ks + 8 * kq);
             const bf16x8 b = *reinterpret_cast<const bf16x8 *>(src + (n + dl) * CP + 8 * cb);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a[mt][ks], b, acc[mt], 0, 0, 0);
         }
-        epi(i, mt * 16 + 4 * kq, n, acc);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            epi(i, mt * 16 + 4 * kq, n, acc[mt]);
     }
+}
+
+// The forward weights of one orientation in registers: the three layers' A
+// fragments and this lane's biases (rows m0 .. m0 + 3 of its accumulators).
+struct FwdW {
+    Frag<96, 1> w1;
+    Frag<96, 1> w2;
+    Frag<160, 2> w3;
+    float b1[4], b2[4], b3[2][4];
+};
+
+// fb: the model's float block (in LDS)
+__device__ __forceinline__ void load_fwd_weights(FwdW &W, const uint8_t *model, bool hz,
+                                                 const float *fb)
+{
+    const __bf16 *A = reinterpret_cast<const __bf16 *>(model) + (hz ? 0 : kC2Orient);
+    W.w1 = load_frag<96, 1>(A + kC2A[0]);
+    W.w2 = load_frag<96, 1>(A + kC2A[1]);
+    W.w3 = load_frag<160, 2>(A + kC2A[2]);
+    const int m0 = 4 * ((threadIdx.x & 63) >> 4);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        W.b1[j] = m0 < 8 ? fb[kC2FB[0] + m0 + j] : 0.0f;
+        W.b2[j] = fb[kC2FB[1] + m0 + j];
+        W.b3[0][j] = fb[kC2FB[2] + m0 + j];
+        W.b3[1][j] = fb[kC2FB[2] + 16 + m0 + j];
+    }
+}
+
+// The model's float block into L.fb (a workgroup-wide copy; the caller
+// synchronises before reading it).
+__device__ void stage_floats(FwdLds &L, const uint8_t *model)
+{
+    const float *src = reinterpret_cast<const float *>(model + kC2FloatsOff);
+    for (int i = threadIdx.x; i < kC2Floats; i += kBlock)
+        L.fb[i] = src[i];
 }
 
 // Input encoding of one band position: colours normalised, coordinates in
@@ -125,10 +195,9 @@ __device__ __forceinline__ bool line_in(uint32_t line_ok, int j) { return (line_
 // positions into L.z (exact where the whole receptive field is inside the
 // window).  line_ok bit j: band line j lies in the frame; positions outside
 // [lo, hi) are beyond the strip.
-__device__ void forward(FwdLds &L, const __bf16 *A, const float *fb, uint32_t line_ok, int lo,
-                        int hi)
+__device__ void forward(FwdLds &L, const FwdW &W, uint32_t line_ok, int lo, int hi)
 {
-    gemm3x3<8, 96, 1, 5>(A + kC2A[0], L.x0, 0, kC2Band, nullptr,
+    gemm3x3<8, 96, 1, 5>(W.w1, L.x0, 0, kC2Band, nullptr,
                          [&](int i, int m0, int n, const f32x4 &acc) {
                              if (m0 >= 8)
                                  return;
@@ -136,31 +205,31 @@ __device__ void forward(FwdLds &L, const __bf16 *A, const float *fb, uint32_t li
                              bf16x4 o;
 #pragma unroll
                              for (int j = 0; j < 4; ++j) {
-                                 const float v = fmaxf(acc[j] + fb[kC2FB[0] + m0 + j], 0.0f);
+                                 const float v = fmaxf(acc[j] + W.b1[j], 0.0f);
                                  o[j] = to_bf16(keep ? v : 0.0f);
                              }
                              *reinterpret_cast<bf16x4 *>(L.h1 + (i * kPos + n + 1) * 8 + m0) = o;
                          });
     __syncthreads();
-    gemm3x3<8, 96, 1, 3>(A + kC2A[1], L.h1, 0, 5, nullptr,
+    gemm3x3<8, 96, 1, 3>(W.w2, L.h1, 0, 5, nullptr,
                          [&](int i, int m0, int n, const f32x4 &acc) {
                              const bool keep = line_in(line_ok, i + 2) && n >= lo && n < hi;
                              bf16x4 o;
 #pragma unroll
                              for (int j = 0; j < 4; ++j) {
-                                 const float v = fmaxf(acc[j] + fb[kC2FB[1] + m0 + j], 0.0f);
+                                 const float v = fmaxf(acc[j] + W.b2[j], 0.0f);
                                  o[j] = to_bf16(keep ? v : 0.0f);
                              }
                              *reinterpret_cast<bf16x4 *>(L.h2 + (i * kPos + n + 1) * 16 + m0) = o;
                          });
     __syncthreads();
-    gemm3x3<16, 160, 2, 1>(A + kC2A[2], L.h2, 0, 3, nullptr,
+    gemm3x3<16, 160, 2, 1>(W.w3, L.h2, 0, 3, nullptr,
                            [&](int, int m0, int n, const f32x4 &acc) {
                                const bool keep = line_in(line_ok, 3) && n >= lo && n < hi;
                                bf16x4 o;
 #pragma unroll
                                for (int j = 0; j < 4; ++j) {
-                                   const float v = fmaxf(acc[j] + fb[kC2FB[2] + m0 + j], 0.0f);
+                                   const float v = fmaxf(acc[j] + W.b3[m0 >> 4][j], 0.0f);
                                    o[j] = to_bf16(keep ? v : 0.0f);
                                }
                                *reinterpret_cast<bf16x4 *>(L.h3 + (n + 1) * 32 + m0) = o;
@@ -169,10 +238,10 @@ __device__ void forward(FwdLds &L, const __bf16 *A, const float *fb, uint32_t li
     const int n = threadIdx.x;
     if (n < kC2Win) {
         const __bf16 *h = L.h3 + (n + 1) * 32;
-        float z = fb[kC2FB4];
+        float z = L.fb[kC2FB4];
 #pragma unroll
         for (int o = 0; o < 32; ++o)
-            z = fmaf(fb[kC2FW4 + o], (float)h[o], z);
+            z = fmaf(L.fb[kC2FW4 + o], (float)h[o], z);
         L.z[n] = z;
     }
     __syncthreads();
@@ -232,36 +301,74 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
     const int L_ = hz ? d.W : d.H;
     const int extent = hz ? d.H : d.W;
     const uint32_t line_ok = band_lines(pos, extent);
-    const __bf16 *A = reinterpret_cast<const __bf16 *>(a.model) + (hz ? 0 : kC2Orient);
-    const float *fb = reinterpret_cast<const float *>(a.model + kC2FloatsOff);
     // guard positions stay zero (every window rewrites the rest)
     clear(L.x0, kC2Band * kPos * 8);
     clear(L.h1, 5 * kPos * 8);
     clear(L.h2, 3 * kPos * 16);
+    stage_floats(L, a.model);
+    __syncthreads();
+    FwdW W;
+    load_fwd_weights(W, a.model, hz, L.fb);
     uint64_t best[2] = {0, 0};
     const int n_win = (L_ + kC2Stride - 1) / kC2Stride;
+
+    // The pixels of a window's band are fetched one window ahead into
+    // registers (band position i = threadIdx.x + q kBlock in slot q), so
+    // their loads are in flight while the previous window's layers run.
+    // Horizontal strips: positions fastest (adjacent pixels of a row);
+    // vertical strips: lines fastest (adjacent pixels of a row).
+    constexpr int kSlots = (kC2Band * kC2Win + kBlock - 1) / kBlock;
+    uint32_t pr[kSlots], pg[kSlots], pb[kSlots];
+    uint32_t have = 0;   // bit q: slot q holds a pixel (else the input is zero)
+    auto fetch = [&](int w) {
+        const int start = w * kC2Stride - kC2Halo;
+        const int lo = start >= 0 ? 0 : -start;
+        const int hi = L_ - start < kC2Win ? L_ - start : kC2Win;
+        have = 0;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            const int j = hz ? i / kC2Win : i % kC2Band;
+            const int n = hz ? i % kC2Win : i / kC2Band;
+            pr[q] = pg[q] = pb[q] = 0;
+            if (i < kC2Band * kC2Win && line_in(line_ok, j) && n >= lo && n < hi) {
+                const int across = pos - 3 + j, along = start + n;
+                const int x = hz ? along : across, y = hz ? across : along;
+                const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
+                pr[q] = px[0];
+                pg[q] = px[1];
+                pb[q] = px[2];
+                have |= 1u << q;
+            }
+        }
+    };
+    fetch(0);
     for (int w = 0; w < n_win; ++w) {
         const int start = w * kC2Stride - kC2Halo;
         const int lo = start >= 0 ? 0 : -start;
         const int hi = L_ - start < kC2Win ? L_ - start : kC2Win;
-        __syncthreads();
-        for (int i = threadIdx.x; i < kC2Band * kC2Win; i += kBlock) {
-            // horizontal: positions fastest (adjacent pixels of a row);
-            // vertical: lines fastest (adjacent pixels of a row)
+        // the previous window's layer 1 (the last reader of x0) is behind
+        // the barriers of its forward pass
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            const int i = threadIdx.x + q * kBlock;
+            if (i >= kC2Band * kC2Win)
+                break;
             const int j = hz ? i / kC2Win : i % kC2Band;
             const int n = hz ? i % kC2Win : i / kC2Band;
             __bf16 *dst = L.x0 + (j * kPos + n + 1) * 8;
-            if (!line_in(line_ok, j) || n < lo || n >= hi) {
+            if (!((have >> q) & 1u)) {
                 *reinterpret_cast<bf16x8 *>(dst) = bf16x8{};
                 continue;
             }
             const int across = pos - 3 + j, along = start + n;
             const int x = hz ? along : across, y = hz ? across : along;
-            const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
-            encode(dst, px[0], px[1], px[2], x, y, d.W, d.H, fb);
+            encode(dst, pr[q], pg[q], pb[q], x, y, d.W, d.H, L.fb);
         }
         __syncthreads();
-        forward(L, A, fb, line_ok, lo, hi);
+        if (w + 1 < n_win)
+            fetch(w + 1);
+        forward(L, W, line_ok, lo, hi);
         const int n = threadIdx.x;
         const int p = start + n;
         if (n >= kC2Halo && n < kC2Win - kC2Halo && p < L_) {
@@ -310,20 +417,22 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_windows(const uint8_t *model,
                                                           int n_windows)
 {
     __shared__ FwdLds L;
-    const float *fb = reinterpret_cast<const float *>(model + kC2FloatsOff);
     clear(L.x0, kC2Band * kPos * 8);
     clear(L.h1, 5 * kPos * 8);
     clear(L.h2, 3 * kPos * 16);
+    stage_floats(L, model);
+    __syncthreads();
+    FwdW W;
     for (int wi = blockIdx.x; wi < n_windows; wi += gridDim.x) {
         const int32_t *g = geom + 8 * wi;
         const bool hz = g[0] != 0;
         const int lo = uniform_int(range[2 * wi]), hi = uniform_int(range[2 * wi + 1]);
         const uint32_t line_ok = band_lines(g[1], hz ? g[4] : g[3]);
         __syncthreads();
-        load_window(L, win + (int64_t)wi * (8 * kC2Win * 3), g, fb, line_ok, lo, hi);
+        load_window(L, win + (int64_t)wi * (8 * kC2Win * 3), g, L.fb, line_ok, lo, hi);
+        load_fwd_weights(W, model, hz, L.fb);
         __syncthreads();
-        forward(L, reinterpret_cast<const __bf16 *>(model) + (hz ? 0 : kC2Orient), fb, line_ok,
-                lo, hi);
+        forward(L, W, line_ok, lo, hi);
         const int n = threadIdx.x;
         if (n >= kTrainHalo && n < kC2Win - kTrainHalo)
             z_out[(int64_t)wi * kTrainOut + n - kTrainHalo] = L.z[n];
@@ -424,7 +533,8 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_grad(Cnn2dTrainArgs a)
     GradLds &G = *reinterpret_cast<GradLds *>(c2_smem);
     FwdLds &L = G.f;
     const __bf16 *lds = reinterpret_cast<const __bf16 *>(&G);
-    const float *fb = reinterpret_cast<const float *>(a.model + kC2FloatsOff);
+    const float *fb = L.fb;
+    stage_floats(L, a.model);
     clear(L.x0, kC2Band * kPos * 8);
     clear(L.h1, 5 * kPos * 8);
     clear(L.h2, 3 * kPos * 16);
@@ -451,8 +561,10 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_grad(Cnn2dTrainArgs a)
         const __bf16 *A = reinterpret_cast<const __bf16 *>(a.model) + (hz ? 0 : kC2Orient);
         __syncthreads();
         load_window(L, a.win + (int64_t)wi * (8 * kC2Win * 3), g, fb, line_ok, lo, hi);
+        FwdW W;
+        load_fwd_weights(W, a.model, hz, fb);
         __syncthreads();
-        forward(L, A, fb, line_ok, lo, hi);
+        forward(L, W, line_ok, lo, hi);
         // logit gradients and the loss (soft binary cross entropy)
         if (t < kC2Win) {
             float dz = 0.0f;
@@ -497,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_grad(Cnn2dTrainArgs a)
         __syncthreads();
         // dP2 = [h2 > 0] (flipped W3 * dP3): output lines 0..2 of layer 2;
         // the dP3 line sits at band line 3, i.e. input line 2 of the GEMM
-        gemm3x3<32, 288, 1, 3>(A + kC2F3, G.dp3, 2, 3, G.zero,
+        gemm3x3<32, 288, 1, 3>(load_frag<288, 1>(A + kC2F3), G.dp3, 2, 3, G.zero,
                                [&](int i, int m0, int n, const f32x4 &v) {
                                    const __bf16 *h = L.h2 + (i * kPos + n + 1) * 16 + m0;
                                    bf16x4 o;
@@ -509,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_grad(Cnn2dTrainArgs a)
         __syncthreads();
         // dP1 = [h1 > 0] (flipped W2 * dP2): lines 0..4 of layer 1; dP2 lines
         // are GEMM input lines 2..4
-        gemm3x3<16, 160, 1, 5>(A + kC2F2, G.dp2, 2, 5, G.zero,
+        gemm3x3<16, 160, 1, 5>(load_frag<160, 1>(A + kC2F2), G.dp2, 2, 5, G.zero,
                                [&](int i, int m0, int n, const f32x4 &v) {
                                    if (m0 >= 8)
                                        return;

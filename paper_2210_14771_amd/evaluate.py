@@ -52,8 +52,9 @@ def edge_points(w: int, h: int, circle: tuple[float, float, float] | None,
 
 
 def hausdorff(a: np.ndarray, b: np.ndarray) -> float:
-    da, _ = cKDTree(b).query(a)
-    db, _ = cKDTree(a).query(b)
+    # exact nearest-neighbour distances; the queries run on every core
+    da, _ = cKDTree(b).query(a, workers=-1)
+    db, _ = cKDTree(a).query(b, workers=-1)
     return float(max(da.max(), db.max()))
 
 

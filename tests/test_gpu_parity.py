@@ -9,7 +9,7 @@ import oracle
 from paper_2210_14771_amd import api, synth
 
 from gpu_helpers import (assert_attempts_equal, assert_points_equal, assert_results_equal,
-                         gen_batch, run_gpu, run_oracle, say)
+                         gen_batch, oracle_params, run_gpu, run_oracle, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -204,6 +204,26 @@ def test_mixed_resolutions_in_one_batch(torch_dev, est):
     for i, f in enumerate(frames):
         r, p = oracle.estimate(f, oracle.params(n_hstrips=32, n_vstrips=32, attempts=1024),
                                uids[i], with_points=True)
+        assert_points_equal(g["pts"][i:i + 1], [p])
+        assert_results_equal(g["res"][i:i + 1], [r])
+
+
+def test_odd_sizes_in_one_batch(torch_dev, est):
+    # 20 frames of small and odd extents (from the 16-pixel minimum, odd
+    # heights, half lines of odd length, a tall narrow frame) in one batch:
+    # every candidate and result equals the oracle's
+    torch = torch_dev
+    sizes = [(16, 40), (33, 64), (63, 48), (64, 96), (65, 80), (97, 120), (129, 64), (1000, 72),
+             (480, 640), (31, 200)] * 2
+    frames = [synth.make_frame(synth.SMALL_640x480, 700 + i, w, h)[0]
+              for i, (h, w) in enumerate(sizes)]
+    devs = [torch.from_numpy(f).cuda() for f in frames]
+    uids = [700 + i for i in range(len(frames))]
+    kw = dict(n_hstrips=8, n_vstrips=12, ransac_attempts=64)
+    say("odd sizes in one batch")
+    g = run_gpu(est, devs, kw, uids, what=("pts", "res"))
+    for i, f in enumerate(frames):
+        r, p = oracle.estimate(f, oracle_params(**kw), uids[i], with_points=True)
         assert_points_equal(g["pts"][i:i + 1], [p])
         assert_results_equal(g["res"][i:i + 1], [r])
 
