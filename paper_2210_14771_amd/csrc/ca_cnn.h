@@ -95,13 +95,16 @@ constexpr int kC2Band = 7;     // lines of a band
 // [dy][dx]; 1: vertical strips, [dx][dy]): bfloat16 GEMM weights A[m][k]
 // with k = (3 da + dl) C_pad + c for the forward convolutions, and flipped
 // weights F[c][(3 da' + dl') C_out + o] = W[o][c][2 - da'][2 - dl'] for the
-// input gradients of layers 2 and 3; then float32 b1, b2, b3, w4 (values of
-// bfloat16), b4, mean, inv_std.
+// input gradients of layers 2 and 3, and layer 1 again for two output lines
+// at once (P[8 s + o][(3 lo + dl) 8 + c] = W1[o][c][lo - s][dl] over the
+// pair's four input lines lo, zero where lo - s is not a tap); then float32
+// b1, b2, b3, w4 (values of bfloat16), b4, mean, inv_std.
 constexpr int kC2KP[3] = {96, 96, 160};          // padded K of the forward GEMMs
 constexpr int kC2A[3] = {0, 16 * 96, 2 * 16 * 96};  // offsets within an orientation
 constexpr int kC2F2 = 2 * 16 * 96 + 32 * 160;    // flipped layer 2: [16][160]
 constexpr int kC2F3 = kC2F2 + 16 * 160;          // flipped layer 3: [16][288]
-constexpr int kC2Orient = kC2F3 + 16 * 288;      // bfloat16 elements per orientation
+constexpr int kC2P1 = kC2F3 + 16 * 288;          // layer 1 by output-line pairs: [16][96]
+constexpr int kC2Orient = kC2P1 + 16 * 96;       // bfloat16 elements per orientation
 constexpr size_t kC2FloatsOff = (size_t)2 * kC2Orient * 2;
 constexpr int kC2FB[3] = {0, 8, 24};             // float offsets of b1, b2, b3
 constexpr int kC2FW4 = 56, kC2FB4 = 88, kC2FMean = 89, kC2FInv = 92;

@@ -147,18 +147,19 @@ struct FwdW {
     float b1[4], b2[4], b3[2][4];
 };
 
-// fb: the model's float block (in LDS)
+// fb: the model's float block (in LDS).  With `paired`, layer 1's weights
+// are those of output-line pairs (rows 8..15 the second line's channels).
 __device__ __forceinline__ void load_fwd_weights(FwdW &W, const uint8_t *model, bool hz,
-                                                 const float *fb)
+                                                 const float *fb, bool paired = false)
 {
     const __bf16 *A = reinterpret_cast<const __bf16 *>(model) + (hz ? 0 : kC2Orient);
-    W.w1 = load_frag<96, 1>(A + kC2A[0]);
+    W.w1 = load_frag<96, 1>(A + (paired ? kC2P1 : kC2A[0]));
     W.w2 = load_frag<96, 1>(A + kC2A[1]);
     W.w3 = load_frag<160, 2>(A + kC2A[2]);
     const int m0 = 4 * ((threadIdx.x & 63) >> 4);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        W.b1[j] = m0 < 8 ? fb[kC2FB[0] + m0 + j] : 0.0f;
+        W.b1[j] = paired ? fb[kC2FB[0] + (m0 & 7) + j] : (m0 < 8 ? fb[kC2FB[0] + m0 + j] : 0.0f);
         W.b2[j] = fb[kC2FB[1] + m0 + j];
         W.b3[0][j] = fb[kC2FB[2] + m0 + j];
         W.b3[1][j] = fb[kC2FB[2] + 16 + m0 + j];
@@ -175,19 +176,22 @@ __device__ void stage_floats(FwdLds &L, const uint8_t *model)
 }
 
 // Input encoding of one band position: colours normalised, coordinates in
-// [-0.5, 0.5]; channels 5..7 are zero.  (x, y) is the pixel, (W, H) the frame.
+// [-0.5, 0.5] as (2 x - (W - 1)) / (2 (W - 1)), taken as a product with the
+// reciprocal rw = 1 / (2 (W - 1)) (and rh for y); channels 5..7 are zero.
+// (x, y) is the pixel, (W, H) the frame.
 __device__ __forceinline__ void encode(__bf16 *dst, uint32_t r, uint32_t g, uint32_t b, int x,
-                                       int y, int W, int H, const float *fb)
+                                       int y, int W, int H, float rw, float rh, const float *fb)
 {
     bf16x8 v;
     v[0] = to_bf16(((float)r - fb[kC2FMean + 0]) * fb[kC2FInv + 0]);
     v[1] = to_bf16(((float)g - fb[kC2FMean + 1]) * fb[kC2FInv + 1]);
     v[2] = to_bf16(((float)b - fb[kC2FMean + 2]) * fb[kC2FInv + 2]);
-    v[3] = to_bf16((float)(2 * x - (W - 1)) / (float)(2 * (W - 1)));
-    v[4] = to_bf16((float)(2 * y - (H - 1)) / (float)(2 * (H - 1)));
+    v[3] = to_bf16((float)(2 * x - (W - 1)) * rw);
+    v[4] = to_bf16((float)(2 * y - (H - 1)) * rh);
     v[5] = v[6] = v[7] = to_bf16(0.0f);
     *reinterpret_cast<bf16x8 *>(dst) = v;
 }
+__device__ __forceinline__ float coord_scale(int extent) { return 1.0f / (float)(2 * (extent - 1)); }
 
 __device__ __forceinline__ bool line_in(uint32_t line_ok, int j) { return (line_ok >> j) & 1u; }
 
@@ -263,7 +267,8 @@ __device__ void load_window(FwdLds &L, const uint8_t *src, const int32_t *g, con
         }
         const uint8_t *px = src + (j * kC2Win + n) * 3;
         const int across = line - 3 + j, along = start + n;
-        encode(dst, px[0], px[1], px[2], hz ? along : across, hz ? across : along, W, H, fb);
+        encode(dst, px[0], px[1], px[2], hz ? along : across, hz ? across : along, W, H,
+               coord_scale(W), coord_scale(H), fb);
     }
 }
 
@@ -281,16 +286,170 @@ __device__ __forceinline__ float sigmoid(float z) { return 1.0f / (1.0f + __expf
 
 // ----------------------------------------------------------- inference --
 
-// Learned candidates: one workgroup per (frame, strip) item, XCD-aware
-// (workgroup b takes item (b % 8) per_xcd + b / 8); the strip's windows in
-// turn, best pixel of each half (ties: outermost).
+// Learned candidates, wave level.  A workgroup takes one (frame, strip) item
+// (XCD-aware: workgroup b takes item (b % 8) per_xcd + b / 8); each of its
+// four waves scores windows of 64 positions of the strip on its own --
+// window w by wave w mod 4 -- with private LDS buffers and the layers'
+// weights in its registers, so no workgroup barrier separates the layers and
+// the waves of a compute unit overlap one another's memory and LDS latency.
+// The pixels of a wave's next window are loaded into registers while its
+// current window's layers run.  The workgroup joins its waves' best pixels
+// per half strip (ties: outermost).
+
+constexpr int kWWin = 64;                        // positions of a wave window
+constexpr int kWPos = kWWin + 2;                 // with a guard position at each end
+constexpr int kWStride = kWWin - 2 * kC2Halo;    // exact logits per wave window
+// A wave's two buffers: P holds the input (7 lines x 8 channels) and later
+// layer 2 (3 x 16), Q layer 1 (5 x 8) and later layer 3 (1 x 32).  Guard
+// positions and rows of one layout read under another hold stale finite
+// values (the buffers are zeroed once); they only feed the 3 halo positions
+// at each window end, whose outputs are discarded.
+constexpr int kWP = kC2Band * kWPos * 8 > 3 * kWPos * 16 ? kC2Band * kWPos * 8 : 3 * kWPos * 16;
+constexpr int kWQ = 5 * kWPos * 8 > kWPos * 32 ? 5 * kWPos * 8 : kWPos * 32;
+struct alignas(16) WaveBufs {
+    __bf16 p[kWP];
+    __bf16 q[kWQ];
+};
+
+// LDS written by some lanes of a wave and read by others next: keep the
+// compiler from moving memory operations across (the hardware keeps a
+// wave's LDS operations in order).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One 3x3 layer over a wave window, all tiles by this wave: for output line
+// i, acc[m][n] = bias[m] + sum_k A[m][k] X[line i + da][n + dl - 1][c] with
+// k = (3 da + dl) CP + c.  The lane's B offsets (its K group of each k-step)
+// are computed once; tiles then differ by constant offsets.  epi(i, nt, mt,
+// acc) receives rows 16 mt + 4 (lane / 16) .. + 3 of column 16 nt + lane % 16.
+// NLO input lines per output index (3; 4 for layer 1 by output-line pairs,
+// whose output index i covers lines 2 i and 2 i + 1: LSTEP = 2).
+template <int CP, int KP, int MT, int OUT_LINES, int NLO = 3, int LSTEP = 1, class Epi>
+__device__ __forceinline__ void wave_gemm3x3(const Frag<KP, MT> &F, const float (&bias)[MT][4],
+                                             const __bf16 *X, Epi epi)
+{
+    const int lane = threadIdx.x & 63;
+    constexpr int NT = kWWin / 16;
+    constexpr int CB = CP / 8;
+    constexpr int G = 3 * NLO * CB;   // real 8-wide K groups; the rest have zero weights
+    constexpr int KS = KP / 32;
+    int boff[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        int g = 4 * ks + (lane >> 4);
+        g = g < G ? g : 0;
+        const int tap = g / CB, cb = g - CB * (g / CB);
+        const int da = tap / 3, dl = tap - 3 * (tap / 3);
+        boff[ks] = ((da * kWPos + dl + (lane & 15)) * CP + 8 * cb);
+    }
+#pragma unroll
+    for (int tile = 0; tile < OUT_LINES * NT; ++tile) {
+        const int nt = tile % NT;
+        const int i = tile / NT;
+        const __bf16 *b0 = X + (LSTEP * i * kWPos + nt * 16) * CP;
+        f32x4 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            acc[mt] = f32x4{bias[mt][0], bias[mt][1], bias[mt][2], bias[mt][3]};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(b0 + boff[ks]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a[mt][ks], b, acc[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            epi(i, nt, mt, acc[mt]);
+    }
+}
+
+// ReLU and the frame / strip mask in one median: clamp to [0, +inf) where
+// the activation exists, to [0, 0] elsewhere; stored as bfloat16.
+__device__ __forceinline__ bf16x4 relu_bf16(const f32x4 &acc, float top)
+{
+    bf16x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        o[j] = to_bf16(__builtin_amdgcn_fmed3f(acc[j], 0.0f, top));
+    return o;
+}
+
+// The 1x1 layer's weights this lane needs (its 8 of layer 3's 32 channels).
+struct OutW {
+    float w4[2][4];
+    float b4;
+};
+
+// Logit of position `lane` of the wave window whose input is in B.p.  The
+// 1x1 layer is folded into layer 3's epilogue: each lane dots its 8
+// channels, the four lane groups holding a position's 32 channels add up by
+// shuffles, and lane group q keeps position tile q.
+__device__ __forceinline__ float wave_forward2d(WaveBufs &B, const FwdW &W, const OutW &O,
+                                                uint32_t line_ok, int lo, int hi)
+{
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, m0 = 4 * (lane >> 4);
+    // tops[nt]: the mask of this lane's column in position tile nt
+    float tops[kWWin / 16];
+#pragma unroll
+    for (int nt = 0; nt < kWWin / 16; ++nt) {
+        const int n = nt * 16 + col;
+        tops[nt] = (n >= lo && n < hi) ? __builtin_inff() : 0.0f;
+    }
+    const float b1[1][4] = {{W.b1[0], W.b1[1], W.b1[2], W.b1[3]}};
+    const float b2[1][4] = {{W.b2[0], W.b2[1], W.b2[2], W.b2[3]}};
+    // layer 1 by output-line pairs (1, 2), (3, 4), (5, -): lane groups 0-1
+    // hold the pair's first line, 2-3 its second
+    wave_gemm3x3<8, 96, 1, 3, 4, 2>(W.w1, b1, B.p, [&](int i, int nt, int, const f32x4 &acc) {
+        const int line = 2 * i + (m0 >> 3);
+        if (line >= 5)
+            return;
+        const float top = line_in(line_ok, line + 1) ? tops[nt] : 0.0f;
+        *reinterpret_cast<bf16x4 *>(B.q + (line * kWPos + nt * 16 + col + 1) * 8 + (m0 & 7)) =
+            relu_bf16(acc, top);
+    });
+    wave_sync();
+    wave_gemm3x3<8, 96, 1, 3>(W.w2, b2, B.q, [&](int i, int nt, int, const f32x4 &acc) {
+        const float top = line_in(line_ok, i + 2) ? tops[nt] : 0.0f;
+        *reinterpret_cast<bf16x4 *>(B.p + (i * kWPos + nt * 16 + col + 1) * 16 + m0) =
+            relu_bf16(acc, top);
+    });
+    wave_sync();
+    float part[kWWin / 16];
+#pragma unroll
+    for (int nt = 0; nt < kWWin / 16; ++nt)
+        part[nt] = 0.0f;
+    const bool mid = line_in(line_ok, 3);
+    wave_gemm3x3<16, 160, 2, 1>(W.w3, W.b3, B.p, [&](int, int nt, int mt, const f32x4 &acc) {
+        const bf16x4 h = relu_bf16(acc, mid ? tops[nt] : 0.0f);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            part[nt] = fmaf(O.w4[mt][j], (float)h[j], part[nt]);
+    });
+    float mine = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < kWWin / 16; ++nt) {
+        float v = part[nt];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        mine = (lane >> 4) == nt ? v : mine;
+    }
+    return O.b4 + mine;
+}
+
 __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
 {
-    __shared__ FwdLds L;
-    __shared__ uint64_t s_best[kBlock / 64][2];
+    __shared__ WaveBufs wb[kWaves];
+    __shared__ float s_fb[kC2Floats];
+    __shared__ uint64_t s_best[kWaves][2];
     const int item = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
     if (item >= a.n_items || (int)(blockIdx.x >> 3) >= a.per_xcd)
         return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int S = a.n_h + a.n_v;
     const int f = uniform_int(a.frame0 + item / S);
     const int st = uniform_int(item % S);
@@ -301,86 +460,99 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
     const int L_ = hz ? d.W : d.H;
     const int extent = hz ? d.H : d.W;
     const uint32_t line_ok = band_lines(pos, extent);
-    // guard positions stay zero (every window rewrites the rest)
-    clear(L.x0, kC2Band * kPos * 8);
-    clear(L.h1, 5 * kPos * 8);
-    clear(L.h2, 3 * kPos * 16);
-    stage_floats(L, a.model);
+    WaveBufs &B = wb[wv];
+    {
+        const float *src = reinterpret_cast<const float *>(a.model + kC2FloatsOff);
+        for (int i = threadIdx.x; i < kC2Floats; i += kBlock)
+            s_fb[i] = src[i];
+        uint4 *z = reinterpret_cast<uint4 *>(&B);
+        for (int i = lane; i < (int)(sizeof(WaveBufs) / 16); i += 64)
+            z[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
     __syncthreads();
     FwdW W;
-    load_fwd_weights(W, a.model, hz, L.fb);
+    load_fwd_weights(W, a.model, hz, s_fb, true);
+    OutW O;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            O.w4[mt][j] = s_fb[kC2FW4 + 16 * mt + 4 * (lane >> 4) + j];
+    O.b4 = s_fb[kC2FB4];
     uint64_t best[2] = {0, 0};
-    const int n_win = (L_ + kC2Stride - 1) / kC2Stride;
+    const int n_win = (L_ + kWStride - 1) / kWStride;
+    const float rw = coord_scale(d.W), rh = coord_scale(d.H);
 
-    // The pixels of a window's band are fetched one window ahead into
-    // registers (band position i = threadIdx.x + q kBlock in slot q), so
-    // their loads are in flight while the previous window's layers run.
-    // Horizontal strips: positions fastest (adjacent pixels of a row);
-    // vertical strips: lines fastest (adjacent pixels of a row).
-    constexpr int kSlots = (kC2Band * kC2Win + kBlock - 1) / kBlock;
+    // This wave's next window's pixels, fetched one window ahead: band
+    // position i = lane + 64 k in slot k (horizontal strips: positions
+    // fastest; vertical strips: lines fastest -- adjacent pixels of a row).
+    constexpr int kSlots = kC2Band * kWWin / 64;
     uint32_t pr[kSlots], pg[kSlots], pb[kSlots];
-    uint32_t have = 0;   // bit q: slot q holds a pixel (else the input is zero)
+    uint32_t have = 0;
+    auto window = [&](int w, int &start, int &lo, int &hi) {
+        start = w * kWStride - kC2Halo;
+        lo = start >= 0 ? 0 : -start;
+        hi = L_ - start < kWWin ? L_ - start : kWWin;
+    };
+    auto slot_pos = [&](int k, int &j, int &n) {
+        const int i = lane + 64 * k;
+        j = hz ? i / kWWin : i % kC2Band;
+        n = hz ? i % kWWin : i / kC2Band;
+    };
     auto fetch = [&](int w) {
-        const int start = w * kC2Stride - kC2Halo;
-        const int lo = start >= 0 ? 0 : -start;
-        const int hi = L_ - start < kC2Win ? L_ - start : kC2Win;
+        int start, lo, hi;
+        window(w, start, lo, hi);
         have = 0;
 #pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
-            const int i = threadIdx.x + q * kBlock;
-            const int j = hz ? i / kC2Win : i % kC2Band;
-            const int n = hz ? i % kC2Win : i / kC2Band;
-            pr[q] = pg[q] = pb[q] = 0;
-            if (i < kC2Band * kC2Win && line_in(line_ok, j) && n >= lo && n < hi) {
+        for (int k = 0; k < kSlots; ++k) {
+            int j, n;
+            slot_pos(k, j, n);
+            pr[k] = pg[k] = pb[k] = 0;
+            if (line_in(line_ok, j) && n >= lo && n < hi) {
                 const int across = pos - 3 + j, along = start + n;
                 const int x = hz ? along : across, y = hz ? across : along;
                 const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
-                pr[q] = px[0];
-                pg[q] = px[1];
-                pb[q] = px[2];
-                have |= 1u << q;
+                pr[k] = px[0];
+                pg[k] = px[1];
+                pb[k] = px[2];
+                have |= 1u << k;
             }
         }
     };
-    fetch(0);
-    for (int w = 0; w < n_win; ++w) {
-        const int start = w * kC2Stride - kC2Halo;
-        const int lo = start >= 0 ? 0 : -start;
-        const int hi = L_ - start < kC2Win ? L_ - start : kC2Win;
-        // the previous window's layer 1 (the last reader of x0) is behind
-        // the barriers of its forward pass
+    if (wv < n_win)
+        fetch(wv);
+    for (int w = wv; w < n_win; w += kWaves) {
+        int start, lo, hi;
+        window(w, start, lo, hi);
 #pragma unroll
-        for (int q = 0; q < kSlots; ++q) {
-            const int i = threadIdx.x + q * kBlock;
-            if (i >= kC2Band * kC2Win)
-                break;
-            const int j = hz ? i / kC2Win : i % kC2Band;
-            const int n = hz ? i % kC2Win : i / kC2Band;
-            __bf16 *dst = L.x0 + (j * kPos + n + 1) * 8;
-            if (!((have >> q) & 1u)) {
+        for (int k = 0; k < kSlots; ++k) {
+            int j, n;
+            slot_pos(k, j, n);
+            __bf16 *dst = B.p + (j * kWPos + n + 1) * 8;
+            if (!((have >> k) & 1u)) {
                 *reinterpret_cast<bf16x8 *>(dst) = bf16x8{};
                 continue;
             }
             const int across = pos - 3 + j, along = start + n;
-            const int x = hz ? along : across, y = hz ? across : along;
-            encode(dst, pr[q], pg[q], pb[q], x, y, d.W, d.H, L.fb);
+            encode(dst, pr[k], pg[k], pb[k], hz ? along : across, hz ? across : along, d.W, d.H,
+                   rw, rh, s_fb);
         }
-        __syncthreads();
-        if (w + 1 < n_win)
-            fetch(w + 1);
-        forward(L, W, line_ok, lo, hi);
-        const int n = threadIdx.x;
-        const int p = start + n;
-        if (n >= kC2Halo && n < kC2Win - kC2Halo && p < L_) {
-            const float sc = sigmoid(L.z[n]);
+        wave_sync();
+        if (w + kWaves < n_win)
+            fetch(w + kWaves);
+        const float z = wave_forward2d(B, W, O, line_ok, lo, hi);
+        const int p = start + lane;
+        if (lane >= kC2Halo && lane < kWWin - kC2Halo && p < L_) {
+            const float sc = sigmoid(z);
             const int half = p < (L_ >> 1) ? 0 : 1;
             const int k = half == 0 ? p : L_ - 1 - p;
             const uint64_t key = ((uint64_t)__float_as_uint(sc) << 32)
                                  | (uint64_t)(0xFFFFFFFFu - (uint32_t)k);
             best[half] = best[half] > key ? best[half] : key;
         }
+        // the next window's input overwrites P, which layer 3 has read
+        wave_sync();
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         uint64_t v = best[half];
@@ -396,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
     if (threadIdx.x < 2) {
         const int half = threadIdx.x;
         uint64_t bb = s_best[0][half];
-        for (int w2 = 1; w2 < kBlock / 64; ++w2)
+        for (int w2 = 1; w2 < kWaves; ++w2)
             bb = bb > s_best[w2][half] ? bb : s_best[w2][half];
         const int k = (int)(0xFFFFFFFFu - (uint32_t)bb);
         const int i = half == 0 ? k : L_ - 1 - k;
@@ -768,7 +940,20 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_pack(const float *master, uint
         float v = 0.0f;
         int l, o, c, da, dl;
         bool real = false;
-        if (e < kC2F2) {
+        if (e >= kC2P1) {
+            // layer 1 for two output lines at once: row m = 8 s + o is output
+            // channel o of the pair's line s; K = (3 lo + dl) 8 + c over the
+            // pair's four input lines lo = 0 .. 3 (tap da = lo - s)
+            const int r = e - kC2P1;
+            const int m = r / 96, k = r % 96;
+            const int g = k / 8, sl = m / 8;
+            l = 0;
+            o = m % 8;
+            c = k % 8;
+            da = g / 3 - sl;
+            dl = g % 3;
+            real = c < cin[0] && da >= 0 && da < 3;
+        } else if (e < kC2F2) {
             l = e < kC2A[1] ? 0 : e < kC2A[2] ? 1 : 2;
             const int r = e - kC2A[l];
             const int m = r / kC2KP[l], k = r % kC2KP[l];
