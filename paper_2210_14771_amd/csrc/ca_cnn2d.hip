@@ -345,25 +345,35 @@ __device__ __forceinline__ void wave_gemm3x3(const Frag<KP, MT> &F, const float 
         const int da = tap / 3, dl = tap - 3 * (tap / 3);
         boff[ks] = ((da * kWPos + dl + (lane & 15)) * CP + 8 * cb);
     }
+    // one output line at a time, its NT position tiles together: their
+    // accumulator chains are independent, so their MFMAs interleave
 #pragma unroll
-    for (int tile = 0; tile < OUT_LINES * NT; ++tile) {
-        const int nt = tile % NT;
-        const int i = tile / NT;
-        const __bf16 *b0 = X + (LSTEP * i * kWPos + nt * 16) * CP;
-        f32x4 acc[MT];
+    for (int i = 0; i < OUT_LINES; ++i) {
+        const __bf16 *b0 = X + LSTEP * i * kWPos * CP;
+        f32x4 acc[NT][MT];
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            acc[mt] = f32x4{bias[mt][0], bias[mt][1], bias[mt][2], bias[mt][3]};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(b0 + boff[ks]);
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a[mt][ks], b, acc[mt], 0, 0, 0);
+                acc[nt][mt] = f32x4{bias[mt][0], bias[mt][1], bias[mt][2], bias[mt][3]};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            bf16x8 b[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                b[nt] = *reinterpret_cast<const bf16x8 *>(b0 + nt * 16 * CP + boff[ks]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.a[mt][ks], b[nt],
+                                                                          acc[nt][mt], 0, 0, 0);
         }
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            epi(i, nt, mt, acc[mt]);
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                epi(i, nt, mt, acc[nt][mt]);
     }
 }
 
@@ -487,7 +497,10 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
     // position i = lane + 64 k in slot k (horizontal strips: positions
     // fastest; vertical strips: lines fastest -- adjacent pixels of a row).
     constexpr int kSlots = kC2Band * kWWin / 64;
-    uint32_t pr[kSlots], pg[kSlots], pb[kSlots];
+    // raw bytes: R | G << 8 and B of each slot, split only when encoded, so
+    // nothing waits for the loads before the next window's turn; slots
+    // outside the frame or the strip load pixel (0, 0) and are dropped
+    uint32_t prg[kSlots], pb[kSlots];
     uint32_t have = 0;
     auto window = [&](int w, int &start, int &lo, int &hi) {
         start = w * kWStride - kC2Halo;
@@ -507,16 +520,15 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
         for (int k = 0; k < kSlots; ++k) {
             int j, n;
             slot_pos(k, j, n);
-            pr[k] = pg[k] = pb[k] = 0;
-            if (line_in(line_ok, j) && n >= lo && n < hi) {
-                const int across = pos - 3 + j, along = start + n;
-                const int x = hz ? along : across, y = hz ? across : along;
-                const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
-                pr[k] = px[0];
-                pg[k] = px[1];
-                pb[k] = px[2];
-                have |= 1u << k;
-            }
+            const bool ok = line_in(line_ok, j) && n >= lo && n < hi;
+            const int across = pos - 3 + j, along = start + n;
+            const int x = ok ? (hz ? along : across) : 0, y = ok ? (hz ? across : along) : 0;
+            const uint8_t *px = frame + (int64_t)y * d.rs + 3 * x;
+            uint16_t rg;
+            __builtin_memcpy(&rg, px, 2);
+            prg[k] = rg;
+            pb[k] = px[2];
+            have |= ok ? 1u << k : 0u;
         }
     };
     if (wv < n_win)
@@ -534,8 +546,8 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_strips(Cnn2dStripArgs a)
                 continue;
             }
             const int across = pos - 3 + j, along = start + n;
-            encode(dst, pr[k], pg[k], pb[k], hz ? along : across, hz ? across : along, d.W, d.H,
-                   rw, rh, s_fb);
+            encode(dst, prg[k] & 0xFFu, prg[k] >> 8, pb[k], hz ? along : across,
+                   hz ? across : along, d.W, d.H, rw, rh, s_fb);
         }
         wave_sync();
         if (w + kWaves < n_win)
