@@ -269,7 +269,7 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
         fl2 = B * cnn2d_flops_per_frame(W, H, kw["n_hstrips"], kw["n_vstrips"])
         rl2 = {"kernel": "k_cnn2d_strips", "bound": "mfma",
                "achieved": fl2 / (ms2 * 1e-3) / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
-               "unit": "TFLOP/s", "traffic": None}
+               "unit": "TFLOP/s", "traffic": measured_traffic("k_cnn2d_strips", "ca_cnn2d.hip")}
         rl2["frac"] = rl2["achieved"] / rl2["peak"]
         learned_2d = {"value": B * (K // G2) * G2 / el2, "unit": "frames/s",
                       "ms_per_step": el2 / ((K // G2) * G2) * 1e3,
