@@ -75,8 +75,9 @@ def parse():
 
 def graph_calls(steps: int, wanted: int, cycle: int) -> int:
     """Calls per captured graph: the largest G <= wanted dividing `steps`
-    that still leaves steps // G >= cycle launches (every context and every
-    resident batch used); 1 when no such G exists."""
+    that still leaves steps // G >= cycle launches (with cycle = the contexts
+    in flight, every context runs); 1 when no such G exists.  The contexts
+    and resident batches a run touches are reported (rotation_used)."""
     for g in range(min(wanted, steps), 0, -1):
         if steps % g == 0 and steps // g >= cycle:
             return g
@@ -178,7 +179,7 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     # as in the headline step: `args.inflight` contexts (each with the model,
     # its own buffers, output and stream) take the graph launches in turn
     n_inflight = max(1, args.inflight)
-    G = graph_calls(K, 10, n_inflight * len(resident))
+    G = graph_calls(K, 10, n_inflight)
     extra = []
     for _ in range(n_inflight - 1):
         e = api.Estimator(0)
@@ -588,7 +589,7 @@ def main():
     # ALU) overlaps the next one's strip loads (HBM); every batch still runs
     # the whole path.
     n_inflight = max(1, args.inflight)
-    G = graph_calls(K, args.graph_calls, n_inflight * len(resident))
+    G = graph_calls(K, args.graph_calls, n_inflight)
     extra = [make_estimator()[0] for _ in range(n_inflight - 1)]
     ests = [est] + extra
     outs = [out] + [torch.empty_like(out) for _ in extra]

@@ -56,16 +56,20 @@ def test_ransac_flops_counts_frames_with_three_points():
 
 
 def test_graph_calls_cover_every_context_and_batch():
-    # 20 steps over 4 contexts and 5 batches: one call per graph
+    # 20 steps over 4 contexts: graphs of 5 calls, 4 launches (one per
+    # context, each on a batch of its own)
+    assert bench.graph_calls(20, 10, 4) == 5
+    assert bench.graph_calls(1000, 10, 4) == 10
+    assert bench.graph_calls(100, 10, 4) == 10
+    assert bench.graph_calls(7, 10, 4) == 1
     assert bench.graph_calls(20, 10, 20) == 1
-    assert bench.graph_calls(1000, 10, 20) == 10
-    assert bench.graph_calls(100, 10, 20) == 5
-    assert bench.graph_calls(7, 10, 20) == 1
     for K in (1, 5, 20, 37, 100, 1000):
-        G = bench.graph_calls(K, 10, 20)
-        assert K % G == 0
-        assert K // G >= 20 or G == 1
+        for cycle in (1, 4, 20):
+            G = bench.graph_calls(K, 10, cycle)
+            assert K % G == 0
+            assert K // G >= cycle or G == 1
     assert bench.rotation_used(20, 4, 5) == {"contexts": 4, "batches": 5}
+    assert bench.rotation_used(4, 4, 5) == {"contexts": 4, "batches": 4}
     assert bench.rotation_used(2, 4, 5) == {"contexts": 2, "batches": 2}
 
 
