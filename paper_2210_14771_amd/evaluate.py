@@ -51,11 +51,25 @@ def edge_points(w: int, h: int, circle: tuple[float, float, float] | None,
     return np.concatenate([arc[keep], rect[inside]])
 
 
+def directed_hausdorff(a: np.ndarray, b: np.ndarray, step: int = 16) -> float:
+    """h(A, B) = max over a of the distance to its nearest point of b, exact.
+
+    Nearest-neighbour queries against every point of b are slow for points
+    far from b, so every a is first measured against the subset b[::step]:
+    that distance u(a) is an upper bound, and u(a) - delta a lower bound,
+    where delta is the largest distance from a point of b to the subset.  So
+    h >= max u - delta, and only the points with u(a) >= max u - delta can
+    attain the maximum; those alone are measured against all of b."""
+    sub = cKDTree(b[::step])
+    delta = sub.query(b, workers=-1)[0].max()
+    u = sub.query(a, workers=-1)[0]
+    cand = u >= u.max() - delta
+    return float(cKDTree(b).query(a[cand], workers=-1)[0].max())
+
+
 def hausdorff(a: np.ndarray, b: np.ndarray) -> float:
-    # exact nearest-neighbour distances; the queries run on every core
-    da, _ = cKDTree(b).query(a, workers=-1)
-    db, _ = cKDTree(a).query(b, workers=-1)
-    return float(max(da.max(), db.max()))
+    """H(A, B) = max(h(A, B), h(B, A)) over the two point sets (Eq. 4)."""
+    return max(directed_hausdorff(a, b), directed_hausdorff(b, a))
 
 
 def normalised_hausdorff(w: int, h: int, gt: tuple[float, float, float] | None,

@@ -29,6 +29,35 @@ def test_matches_scipy_directed_hausdorff():
     assert abs(ev.hausdorff(a, b) - ref) < 1e-9
 
 
+def test_directed_distance_equals_brute_force():
+    # the subset bound only prunes points that cannot attain the maximum:
+    # scattered clouds, clustered clouds and curves, several subset steps
+    rng = np.random.default_rng(3)
+    for trial in range(24):
+        na, nb = rng.integers(1, 900, 2)
+        a = rng.normal(0, rng.uniform(1, 50), (na, 2)) + rng.uniform(-80, 80, 2)
+        if trial % 3 == 0:
+            t = rng.uniform(0, 2 * np.pi, nb)
+            b = np.stack([np.cos(t), np.sin(t)], 1) * rng.uniform(5, 60)
+        else:
+            b = rng.normal(0, rng.uniform(1, 50), (nb, 2))
+        brute = np.sqrt(((a[:, None, :] - b[None, :, :]) ** 2).sum(-1)).min(1).max()
+        for step in (1, 2, 7, 16, 64):
+            assert abs(ev.directed_hausdorff(a, b, step) - brute) < 1e-9, (trial, step)
+
+
+def test_far_concentric_and_missing_estimates_match_scipy():
+    # the cases the bound is for: estimates far from the truth, a missing
+    # estimate (the rectangle), concentric circles a few pixels apart
+    w, h = 160, 90
+    gt = (83.0, 43.0, 49.5)
+    for est in (gt, (83.2, 42.9, 49.8), (83.0, 43.0, 54.0), (83.0, 43.0, 69.5),
+                (30.0, 60.0, 12.0), (150.0, -20.0, 40.0), None):
+        a, b = ev.edge_points(w, h, gt), ev.edge_points(w, h, est)
+        ref = max(directed_hausdorff(a, b)[0], directed_hausdorff(b, a)[0])
+        assert abs(ev.hausdorff(a, b) - ref) < 1e-9, est
+
+
 def test_normalisation_eq6():
     # 640x480 frame: 1 native px counts as 2202.9 / 800 normalised px
     got = ev.normalised_hausdorff(640, 480, (320, 240, 100), (320, 240, 101))

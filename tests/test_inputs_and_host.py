@@ -134,3 +134,40 @@ def test_drifting_circle_steps():
     assert np.all((jumps < 1e-12) | (np.abs(jumps - 0.1) < 0.02) | (np.abs(jumps - 1 / 11) < 0.02))
     assert all(rr.grids is recs[0].grids for rr in recs)   # the same tissue
     assert len({rr.key for rr in recs}) == len(recs)       # fresh noise
+
+
+def test_serving_accuracy_is_sampled_with_progress():
+    """The serving benchmark evaluates accuracy on an evenly spaced sample of
+    the served frames and logs every block of frames, so the host-side
+    evaluation after a serving run never goes silent for long; the sample's
+    errors are those of a direct evaluation of the same frames."""
+    from paper_2210_14771_amd import evaluate, serve_bench
+
+    rng = np.random.default_rng(7)
+    streams, served = [], []
+    for sid, (w, h) in enumerate(((96, 64), (128, 72), (80, 80))):
+        recs = serve.drifting_recipes(sid, w, h, 4, rng)
+        streams.append(serve.SimStream(sid, w, h, 30.0, [None] * 4, [r.spec for r in recs],
+                                       np.zeros(0)))
+        for seq in range(25):
+            spec = recs[seq % 4].spec
+            valid = int(seq % 3 != 0)
+            res = (spec.cx + rng.normal(0, 2), spec.cy + rng.normal(0, 2), spec.r * 0.97, 0.5,
+                   10, 20, valid, 0 if valid else 2)
+            filt = (1, spec.cx + 1.0, spec.cy, spec.r + 0.5, 2.0)
+            served.append({"stream": sid, "seq": seq, "result": res, "filtered": filt})
+    rng.shuffle(served)
+    sample = serve_bench.accuracy_sample(served, 20)
+    keys = [(r["stream"], r["seq"]) for r in sample]
+    assert len(sample) == 20 and keys == sorted(keys) and len(set(keys)) == 20
+    assert keys[0] == (0, 0) and keys[-1] == (2, 24)            # both ends of the order
+    assert serve_bench.accuracy_sample(served, 500) == sorted(
+        served, key=lambda r: (r["stream"], r["seq"]))
+    lines = []
+    acc = serve_bench.accuracy(sample, streams, lines.append, block=6)
+    assert len(lines) == 2 * 4                                   # ceil(20 / 6) per kind
+    assert lines[3] == "accuracy (frame): 20 of 20 frames"
+    specs = [streams[r["stream"]].specs[r["seq"] % 4] for r in sample]
+    a = np.array([r["result"] for r in sample], dtype=np.float64)
+    e = evaluate.frame_errors(specs, a[:, 0], a[:, 1], a[:, 2], a[:, 6] != 0)
+    assert acc["frame"] == evaluate.summarise(e)
