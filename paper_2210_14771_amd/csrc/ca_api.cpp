@@ -372,14 +372,17 @@ int32_t ransac_lanes(const ca_ctx *ctx, int32_t n, int32_t attempts)
     return lanes;
 }
 
+// keep: the learned results when this is the handcrafted pass of the
+// fallback (frames whose learned result stands are skipped; that pass takes
+// the split schedule, whose kernels implement the skip), else null.
 int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
                 ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
-                bool timed)
+                bool timed, const ca_result *keep = nullptr, float keep_frac = 0.0f)
 {
     const bool fused = ctx->schedule == CA_SCHEDULE_FUSED
                        || (ctx->schedule == CA_SCHEDULE_AUTO
                            && pl->tuned_schedule == CA_SCHEDULE_FUSED);
-    const bool fused_path = fused && p.scorer == CA_SCORER_HANDCRAFTED;
+    const bool fused_path = fused && p.scorer == CA_SCORER_HANDCRAFTED && !keep;
     // the persistent kernel takes attempt groups of two lanes per attempt
     const int32_t lanes =
         fused_path ? ca::kLanesPerAttempt : ransac_lanes(ctx, n, p.ransac_attempts);
@@ -401,6 +404,8 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     sa.frame0 = 0;
     sa.frame_list = nullptr;
     sa.items_per_group = 1;
+    sa.keep = keep;
+    sa.keep_frac = keep_frac;
 
     ca::RansacArgs ra;
     ra.fd = pl->fd;
@@ -422,6 +427,8 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     ra.lanes = lanes;
     ra.frame0 = 0;
     ra.groups_done = pl->ctl + ca::kCtlFrames + n;
+    ra.keep = keep;
+    ra.keep_frac = keep_frac;
 
     ca::SelectArgs se;
     se.rec = pl->rec;
@@ -546,7 +553,9 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
 
 // One call: the learned scorer's pipeline, then, with a fallback fraction,
 // the handcrafted pipeline into the plan's second result array and a
-// per-frame choice between the two.
+// per-frame choice between the two.  The handcrafted kernels skip the frames
+// whose learned result stands (the same rule as the choice), so that pass
+// costs in proportion to the frames that fall back.
 int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_params &p,
             ca_point *points_out, ca_attempt *attempts_out, ca_result *out, hipStream_t s,
             bool timed)
@@ -557,7 +566,8 @@ int enqueue(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const ca_pa
     ca_params h = p;
     h.scorer = CA_SCORER_HANDCRAFTED;
     h.fallback_inlier_frac = 0.0f;
-    rc = enqueue_one(ctx, pl, frames, n, h, nullptr, nullptr, pl->res2, s, false);
+    rc = enqueue_one(ctx, pl, frames, n, h, nullptr, nullptr, pl->res2, s, false, out,
+                     p.fallback_inlier_frac);
     if (rc != CA_OK)
         return rc;
     return ca::launch_fallback(out, pl->res2, n, p.fallback_inlier_frac, s) == hipSuccess

@@ -53,6 +53,11 @@ struct StripArgs {
     int32_t frame0;         // first frame of this launch (items cover frames frame0 ..)
     const int32_t *frame_list;  // or the frames of this launch (null: frame0, frame0 + 1, ..)
     int32_t items_per_group;    // strip items one workgroup takes in turn (tables loaded once)
+    // With keep set (the handcrafted pass of the learned scorer's fallback),
+    // frames whose learned result keep[f] stands under the fallback rule at
+    // keep_frac are skipped: their handcrafted result is never used.
+    const ca_result *keep = nullptr;
+    float keep_frac = 0.0f;
 };
 
 struct RansacArgs {
@@ -72,6 +77,8 @@ struct RansacArgs {
     int32_t lanes;          // lanes per attempt: 2, 4, 8 or 16
     int32_t frame0;         // first frame of this launch (blockIdx.y counts from it)
     uint32_t *groups_done;  // per frame: groups finished (the last one selects), or null
+    const ca_result *keep = nullptr;   // as in StripArgs: frames to skip
+    float keep_frac = 0.0f;
 };
 
 struct SelectArgs {

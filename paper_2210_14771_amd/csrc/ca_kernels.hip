@@ -824,6 +824,15 @@ __device__ void load_tables(const StripArgs &a, uint8_t *smem)
         dst[i] = a.lut[i];
 }
 
+// The fallback rule of the learned scorer: a frame keeps its learned result
+// unless its best circle explains fewer than `frac` of its kept points, or
+// fewer than three points were kept.  k_fallback applies it; the handcrafted
+// pass before it skips the frames it keeps, by the same expression.
+__device__ __forceinline__ bool learned_kept(const ca_result &r, float frac)
+{
+    return !(r.n_points < 3 || (float)r.inliers < frac * (float)r.n_points);
+}
+
 __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -838,6 +847,12 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
     const int first = ((b & 7) * a.per_xcd + (b >> 3)) * a.items_per_group;
     if (first >= a.n_items)
         return;
+    const int S0 = a.n_h + a.n_v;
+    if (a.keep && a.items_per_group == 1) {
+        const int k = first / S0;
+        if (learned_kept(a.keep[a.frame_list ? a.frame_list[k] : a.frame0 + k], a.keep_frac))
+            return;
+    }
     load_tables(a, smem);
     const int S = a.n_h + a.n_v;
     const StripLds c = carve_strip_lds(smem, a.sg_len, s_scan, s_best);
@@ -846,7 +861,10 @@ __global__ __launch_bounds__(kBlock) void k_strips(StripArgs a)
         if (item >= a.n_items)
             break;
         const int k = item / S;
-        strip_work(a, c, a.frame_list ? a.frame_list[k] : a.frame0 + k, item % S);
+        const int f = a.frame_list ? a.frame_list[k] : a.frame0 + k;
+        if (a.keep && learned_kept(a.keep[f], a.keep_frac))
+            continue;
+        strip_work(a, c, f, item % S);
     }
 }
 
@@ -858,6 +876,8 @@ __global__ __launch_bounds__(kBlock) void k_ransac(RansacArgs a, SelectArgs sel)
     __shared__ Lds L;
     __shared__ int s_last;
     const int f = a.frame0 + (int)blockIdx.y;
+    if (a.keep && learned_kept(a.keep[f], a.keep_frac))
+        return;   // no group of this frame counts or selects
     ransac_work<LANES>(a, L, f, blockIdx.x);
     if (threadIdx.x == 0)
         s_last = add_dev(a.groups_done + f, 1u) == (uint32_t)(a.groups - 1);
@@ -999,8 +1019,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback(ca_result *out, const ca_re
     const int f = blockIdx.x * kBlock + threadIdx.x;
     if (f >= n)
         return;
-    const ca_result a = out[f];
-    if (a.n_points < 3 || (float)a.inliers < frac * (float)a.n_points) {
+    if (!learned_kept(out[f], frac)) {
         ca_result b = fb[f];
         b.reason += CA_REASON_FALLBACK;
         out[f] = b;

@@ -400,9 +400,12 @@ hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t)
     const int32_t S = a.n_h + a.n_v;
     if (lds_bytes < strip_lds_bytes(a.sg_len, a.line_pitch))
         fail("strip launch %s", "with too little LDS");
-    for (int32_t k = 0; k < a.n_items / S; ++k)
-        check_frame(a.frames, a.fd, a.strips, a.frame_list ? a.frame_list[k] : a.frame0 + k,
-                    a.n_h, a.n_v, a.line_pitch);
+    for (int32_t k = 0; k < a.n_items / S; ++k) {
+        const int32_t f = a.frame_list ? a.frame_list[k] : a.frame0 + k;
+        check_frame(a.frames, a.fd, a.strips, f, a.n_h, a.n_v, a.line_pitch);
+        if (a.keep)
+            check_device(a.keep + f, sizeof(ca_result), "learned results to keep");
+    }
     return hipSuccess;
 }
 hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t)
@@ -414,6 +417,9 @@ hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frame
                  "records");
     if (a.groups_done)
         check_device(a.groups_done + a.frame0, sizeof(uint32_t) * (size_t)n_frames, "counters");
+    if (a.keep)
+        check_device(a.keep + a.frame0, sizeof(ca_result) * (size_t)n_frames,
+                     "learned results to keep");
     write_results(sel.out, a.frame0, n_frames);
     return hipSuccess;
 }

@@ -46,7 +46,7 @@ def hard(torch_dev):
 
 def _raw(est, frames, params):
     import torch
-    r = est.estimate_area(frames, params, list(range(frames.shape[0])))
+    r = est.estimate_area(frames, params, list(range(len(frames))))
     torch.cuda.synchronize()
     return r.raw.cpu().numpy()
 
@@ -69,6 +69,44 @@ def test_fallback_selects_per_frame_by_inlier_fraction(torch_dev, est, hard):
     # frac 0 is no fallback
     np.testing.assert_array_equal(
         _raw(est, frames, api.default_params(**KW, scorer=1, fallback_inlier_frac=0.0)), learned)
+
+
+def test_fallback_pass_skips_kept_frames_under_every_schedule(torch_dev, est, hard):
+    """The handcrafted pass of the fallback runs only on the frames whose
+    learned result falls back (its kernels skip the others); the results are
+    the per-frame choice between a learned-only and a handcrafted-only call
+    under the split schedule, the persistent one (whose fallback pass takes
+    the split kernels), two pipelined sub-batches and strip tiles of 3, for
+    a batch of one shape and a batch of two shapes."""
+    frames = hard[0][:24]
+    two_shapes = [frames[i] if i % 2 else frames[i][:720, :1280] for i in range(24)]
+    frac = 0.5
+    cases = (("split", {}), ("persistent", {"schedule": "fused"}), ("pipeline 2", {"pipeline": 2}),
+             ("tiles of 3", {"strips_per_group": 3}))
+    n_fallback = 0
+    for label, inputs in (("1080p", frames), ("two shapes", two_shapes)):
+        learned = _raw(est, inputs, api.default_params(**KW, scorer=1))
+        plain = _raw(est, inputs, api.default_params(**KW))
+        want = learned.copy()
+        for i in range(len(want)):
+            inl, npts = learned[i, 4], learned[i, 5]
+            if npts < 3 or np.float32(inl) < np.float32(frac) * np.float32(npts):
+                want[i] = plain[i]
+                want[i, 7] += 256
+                n_fallback += 1
+        say(f"{label}: {int(((want[:, 7] & 256) != 0).sum())} of {len(want)} frames fall back")
+        for name, opts in cases:
+            saved = {k: est.get_option(k) for k in opts}
+            for k, v in opts.items():
+                est.set_option(k, v)
+            try:
+                got = _raw(est, inputs,
+                           api.default_params(**KW, scorer=1, fallback_inlier_frac=frac))
+            finally:
+                for k, v in saved.items():
+                    est.set_option(k, v)
+            np.testing.assert_array_equal(got, want, err_msg=f"{label}, {name}")
+    assert 0 < n_fallback < 48          # both kinds of frame were present
 
 
 def test_learned_calls_are_deterministic(torch_dev, est, hard):
