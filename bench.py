@@ -134,6 +134,13 @@ def measured_traffic(kernel: str, source: str = "ca_kernels.hip"):
     return int(m.group(1))
 
 
+def strip_kernel(n_h: int, n_v: int, tiles: int = 1) -> str:
+    """The strip kernel a split call launches: strips in pairs (one
+    workgroup per two strips) when both counts are even and each workgroup
+    takes one item, else one strip per workgroup item."""
+    return "k_strips_pair" if tiles <= 1 and n_h % 2 == 0 and n_v % 2 == 0 else "k_strips"
+
+
 BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix
 
 
@@ -681,11 +688,14 @@ def main():
         kernels = {"k_" + k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]}
                    for k, v in kt.items() if k != "unused"}
         dominant = "strips" if strips_ms >= ransac_ms else "ransac"
-    traffic = measured_traffic("k_strips") if schedule_used == "split" else None
+    skern = strip_kernel(kw["n_hstrips"], kw["n_vstrips"], max(tiles.values(), default=1))
+    if schedule_used != "fused" and "k_strips" in kernels:
+        kernels[skern] = kernels.pop("k_strips")
+    traffic = measured_traffic(skern) if schedule_used == "split" else None
     rl_strips = {"bound": "hbm", "achieved": algo_bytes / (strips_ms * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "traffic": traffic,
                  "traffic_note": "bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                 "copy-calibrated (profiles/k_strips_64x1080p_hbm_traffic.md)"}
+                                 f"copy-calibrated (profiles/{skern}_64x1080p_hbm_traffic.md)"}
     if traffic:
         rl_strips["traffic_gbps"] = traffic / (strips_ms * 1e-3) / 1e9
     rl_strips["frac"] = rl_strips["achieved"] / rl_strips["peak"]
@@ -700,7 +710,7 @@ def main():
                                 "pass, 9 per point in the final pass)"}
     rl_ransac["frac"] = rl_ransac["achieved"] / rl_ransac["peak"]
     roofline = dict(rl_ransac if dominant == "ransac" else rl_strips)
-    roofline["kernel"] = {"fused": "k_fused", "strips": "k_strips", "ransac": "k_ransac"}[dominant]
+    roofline["kernel"] = {"fused": "k_fused", "strips": skern, "ransac": "k_ransac"}[dominant]
 
     line = {
         "metric": METRIC,

@@ -61,7 +61,9 @@ typedef struct ca_ctx ca_ctx;
 typedef struct {
     int32_t width, height;   /* pixels, each in [16, CA_MAX_EXTENT] */
     int32_t row_stride;      /* bytes between the starts of two rows, >= 3 * width */
-    int32_t pixel_stride;    /* bytes between pixels; must be 3 */
+    int32_t pixel_stride;    /* bytes between pixels; must be 3 (packed RGB; planar or padded
+                                pixels, and a separate stride between channels, are not
+                                supported: other values return CA_E_UNSUPPORTED) */
     int64_t byte_offset;     /* first byte of the frame relative to `frames_dev`, >= 0;
                                 bytes [byte_offset, byte_offset + (height - 1) * row_stride
                                 + 3 * width) must lie in the caller's allocation (the

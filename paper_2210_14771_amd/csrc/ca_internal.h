@@ -9,7 +9,8 @@
 
 namespace ca {
 
-constexpr int kBlock = 256;      // threads per workgroup of every kernel
+constexpr int kBlock = 256;      // threads per workgroup (k_strips_pair: two strips, 2 kBlock)
+constexpr size_t kPairLdsMax = 65536;  // LDS bytes the paired strip kernel may take
 constexpr int kHalfThreads = 128; // threads per half strip
 constexpr int kLanesPerAttempt = 2;   // lanes sharing one RANSAC attempt (fused schedule, and
                                       // the split schedule when a batch fills the device)

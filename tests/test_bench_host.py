@@ -101,3 +101,11 @@ def test_traffic_summary_missing(tmp_path, monkeypatch):
 
 if __name__ == "__main__":
     sys.exit(pytest.main([__file__, "-q"]))
+
+
+def test_strip_kernel_name_follows_the_pairing_rule():
+    # strips go in pairs when both counts are even and a workgroup takes one item
+    assert bench.strip_kernel(32, 32) == "k_strips_pair"
+    assert bench.strip_kernel(16, 0) == "k_strips_pair"
+    assert bench.strip_kernel(32, 31) == "k_strips"
+    assert bench.strip_kernel(32, 32, tiles=2) == "k_strips"
