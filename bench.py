@@ -394,6 +394,7 @@ def mixed_section(args, est, kw):
     est.set_option("schedule", "auto")
     tuned = est.autotune(views, params, uids, reps=5)
     chosen = est.last_tuned_schedule
+    chosen_pipeline = est.last_tuned_pipeline
     out = torch.empty((n, 8), dtype=torch.int32, device="cuda")
     K = args.mixed_steps
 
@@ -424,7 +425,7 @@ def mixed_section(args, est, kw):
                         "one HIP graph launch per step",
             "value": n * K / elapsed, "unit": "frames/s", "ms_per_step": elapsed / K * 1e3,
             "steps": K, "hbm_gbps_algorithmic": algo * K / elapsed / 1e9,
-            "autotuned": {"schedule": chosen,
+            "autotuned": {"schedule": chosen, "pipeline": chosen_pipeline,
                           "strips_per_group": {f"{w}x{h}": t for (w, h), t in sorted(tuned.items())}},
             "ms_per_step_by_schedule": {"split_tile1": split_t1 / K * 1e3,
                                         "split_tuned_tiles": split_tuned / K * 1e3,
@@ -569,7 +570,7 @@ def main():
     tuning = None
     if args.schedule == "auto":
         schedule_used = est.last_tuned_schedule or "split"
-        tuning = {"schedule": schedule_used,
+        tuning = {"schedule": schedule_used, "pipeline": est.last_tuned_pipeline,
                   "strips_per_group": {f"{w}x{h}": t for (w, h), t in tiles.items()}}
     else:
         schedule_used = args.schedule
@@ -750,7 +751,8 @@ def main():
         "eager_ms_per_step": elapsed_eager / K * 1e3,
         "schedule": schedule_used,
         "autotune": tuning,
-        "pipeline": pipeline if schedule_used == "split" else None,
+        "pipeline": ((pipeline or (est.last_tuned_pipeline if args.schedule == "auto" else 1) or 1)
+                     if schedule_used == "split" else None),
         "kernel_timing": "one launch per kernel for the whole batch (pipeline 1)",
         "kernels": kernels,
         "roofline": roofline,

@@ -381,7 +381,9 @@ void ca_graph_destroy(ca_graph *graph);
 #define CA_OPT_PIPELINE 6      /* split: sub-batches per call, alternating over two
                                   internal streams forked from and joined into the
                                   caller's stream (1 = everything on the caller's
-                                  stream, the default and the fastest measured) */
+                                  stream); 0 (default) = under CA_SCHEDULE_AUTO the
+                                  count ca_autotune measured fastest for the batch
+                                  (1, 2 or 4), else 1 */
 #define CA_OPT_STRIPS_PER_GROUP 7  /* split: strip items per workgroup tile, 1..16, for
                                       every frame shape; 0 (default) = the autotuned value
                                       of each shape (ca_autotune), else 1 */
@@ -394,8 +396,8 @@ void ca_graph_destroy(ca_graph *graph);
                                   whose last group per frame selects the circle */
 #define CA_SCHEDULE_FUSED 1    /* one persistent launch drawing both kinds of work from
                                   per-XCD queues; same results */
-#define CA_SCHEDULE_AUTO 2     /* per batch the schedule ca_autotune measured faster
-                                  (split when the batch was not tuned) */
+#define CA_SCHEDULE_AUTO 2     /* per batch the schedule ca_autotune measured fastest
+                                  (split in one call when the batch was not tuned) */
 
 /* Autotuner of the split schedule's strip tiles.  A workgroup of the strip
  * kernel stages the score tables in LDS once and then scores T strip items
@@ -405,14 +407,21 @@ void ca_graph_destroy(ca_graph *graph);
  * launches of the strip kernel per candidate T with HIP events and keeps
  * the fastest for (width, height, n_hstrips, n_vstrips) in the context.
  * Then (handcrafted scorer) it times `reps` whole calls of the batch under
- * the split schedule with those tiles and under the persistent fused
- * schedule, and keeps the faster for this batch (used with
- * CA_SCHEDULE_AUTO); *schedule_out (may be NULL) receives it.  Later calls
- * (and graphs captured later) use the results.  Blocking.  Results never
- * depend on T or on the schedule. */
+ * the split schedule with those tiles, in one call and in 2 and 4 pipelined
+ * sub-batches (CA_OPT_PIPELINE), and under the persistent fused schedule,
+ * and keeps the fastest for this batch (used with CA_SCHEDULE_AUTO and the
+ * pipeline option at 0); *schedule_out (may be NULL) receives its schedule,
+ * ca_get_last_autotune the schedule and sub-batch count.  Later calls (and
+ * graphs captured later) use the results.  Blocking.  Results never depend
+ * on T, on the sub-batches or on the schedule. */
 int ca_autotune(ca_ctx *ctx, const uint8_t *frames_dev, const ca_frame_desc *dims_host,
                 int32_t n_frames, const ca_params *params, int32_t reps, void *stream,
                 int32_t *schedule_out);
+
+/* What the last ca_autotune of this context chose for its batch: the
+ * schedule (CA_SCHEDULE_SPLIT or CA_SCHEDULE_FUSED; -1 before any) and the
+ * sub-batches of its split calls (0 before any).  Host pointers. */
+int ca_get_last_autotune(ca_ctx *ctx, int32_t *schedule, int32_t *pipeline);
 
 /* The tuned T of a frame shape and strip counts (0 if not tuned). */
 int ca_get_tuning(ca_ctx *ctx, int32_t width, int32_t height, int32_t n_hstrips,

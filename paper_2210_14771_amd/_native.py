@@ -34,7 +34,7 @@ EXPORTS = ("ca_default_params", "ca_create", "ca_destroy", "ca_estimate_area",
            "ca_cnn_window_logits", "ca_cnn_gradients", "ca_cnn_sgd_step", "ca_selftest_mfma",
            "ca_set_model_2d", "ca_get_model_2d", "ca_set_momentum_2d", "ca_cnn2d_window_logits",
            "ca_cnn2d_gradients", "ca_cnn2d_sgd_step",
-           "ca_autotune", "ca_get_tuning", "ca_server_create", "ca_server_destroy",
+           "ca_autotune", "ca_get_tuning", "ca_get_last_autotune", "ca_server_create", "ca_server_destroy",
            "ca_server_open", "ca_server_close", "ca_server_submit", "ca_server_step",
            "ca_server_stats",
            "ca_error_string", "ca_version")
@@ -175,6 +175,7 @@ def lib() -> C.CDLL:
         L.ca_server_step.argtypes = [vp, vp, i32, C.POINTER(C.c_int32)]
         L.ca_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
         L.ca_get_tuning.argtypes = [vp, i32, i32, i32, i32, C.POINTER(C.c_int32)]
+        L.ca_get_last_autotune.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.ca_set_option.argtypes = [vp, i32, C.c_int64]
         L.ca_get_option.argtypes = [vp, i32, C.POINTER(C.c_int64)]
         L.ca_device_status.argtypes = [vp]

@@ -410,7 +410,9 @@ class Estimator:
 
     def autotune(self, frames, params=None, frame_uids=None, reps: int = 5) -> dict:
         """Tune the strip tile (strip items per workgroup) of every frame shape
-        in the batch; returns {(width, height): T}."""
+        in the batch, then the batch's schedule (split in 1, 2 or 4 pipelined
+        sub-batches, or persistent: last_tuned_schedule, last_tuned_pipeline);
+        returns {(width, height): T}."""
         base, descs, n, p, s = self._prep(frames, params, frame_uids, None)
         sched = C.c_int32(-1)
         N.check(N.lib().ca_autotune(self._ctx, C.c_void_p(base), descs, n, C.byref(p), reps,
@@ -421,6 +423,10 @@ class Estimator:
             if key not in out:
                 out[key] = self.get_tuning(key[0], key[1], p.n_hstrips, p.n_vstrips)
         self.last_tuned_schedule = {0: "split", 1: "fused"}.get(sched.value)
+        s2, pipe = C.c_int32(), C.c_int32()
+        N.check(N.lib().ca_get_last_autotune(self._ctx, C.byref(s2), C.byref(pipe)),
+                "ca_get_last_autotune")
+        self.last_tuned_pipeline = int(pipe.value) if self.last_tuned_schedule == "split" else None
         return out
 
     def get_tuning(self, width: int, height: int, n_hstrips: int, n_vstrips: int) -> int:

@@ -517,7 +517,9 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
         return ok && (!mid || hipEventRecord(mid, st) == hipSuccess)
                && ca::launch_ransac(r2, se, f1 - f0, st) == hipSuccess;
     };
-    const int32_t nsub = ctx->pipeline > 1 ? (int32_t)std::min<int64_t>(ctx->pipeline, n) : 1;
+    const int64_t want = ctx->pipeline > 0 ? ctx->pipeline
+                         : (ctx->schedule == CA_SCHEDULE_AUTO ? pl->tuned_pipeline : 1);
+    const int32_t nsub = want > 1 ? (int32_t)std::min<int64_t>(want, n) : 1;
     if (nsub == 1) {
         if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
             || !launch_range(0, n, s, ev ? ev[1] : nullptr)
@@ -1272,31 +1274,60 @@ int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, i
         ctx->tuned[{c.W, c.H, p.n_hstrips, p.n_vstrips}] = best_t;
     }
     // whole calls of this batch: the split schedule (with the tiles just
-    // chosen) against the persistent one; the faster serves CA_SCHEDULE_AUTO
+    // chosen) in one call or cut into 2 or 4 pipelined sub-batches, against
+    // the persistent one; the fastest serves CA_SCHEDULE_AUTO (with the
+    // pipeline option at 0)
     if (rc == CA_OK && p.scorer == CA_SCORER_HANDCRAFTED) {
-        const int64_t saved = ctx->schedule;
-        float ms[2] = {0.0f, 0.0f};
-        const int64_t cand[2] = {CA_SCHEDULE_SPLIT, CA_SCHEDULE_FUSED};
-        for (int k = 0; k < 2 && rc == CA_OK; ++k) {
-            ctx->schedule = cand[k];
+        const int64_t saved_schedule = ctx->schedule, saved_pipeline = ctx->pipeline;
+        struct Trial {
+            int64_t schedule, pipeline;
+        };
+        const Trial trials[4] = {{CA_SCHEDULE_SPLIT, 1}, {CA_SCHEDULE_SPLIT, 2},
+                                 {CA_SCHEDULE_SPLIT, 4}, {CA_SCHEDULE_FUSED, 1}};
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int k = 0; k < 4 && rc == CA_OK; ++k) {
+            if (trials[k].pipeline > n)
+                continue;
+            ctx->schedule = trials[k].schedule;
+            ctx->pipeline = trials[k].pipeline;
             bool ok = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, st, false) == CA_OK
                       && hipEventRecord(e0, st) == hipSuccess;
             for (int32_t r = 0; ok && r < reps; ++r)
                 ok = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, st, false) == CA_OK;
+            float ms = 0.0f;
             ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess
-                 && hipEventElapsedTime(&ms[k], e0, e1) == hipSuccess;
+                 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
             if (!ok)
                 rc = CA_E_DEVICE;
+            else if (k == 0 || ms < best_ms) {
+                best = k;
+                best_ms = ms;
+            }
         }
-        ctx->schedule = saved;
-        if (rc == CA_OK)
-            pl->tuned_schedule = ms[1] < ms[0] ? CA_SCHEDULE_FUSED : CA_SCHEDULE_SPLIT;
+        ctx->schedule = saved_schedule;
+        ctx->pipeline = saved_pipeline;
+        if (rc == CA_OK) {
+            pl->tuned_schedule = (int32_t)trials[best].schedule;
+            pl->tuned_pipeline = (int32_t)trials[best].pipeline;
+            ctx->last_schedule = pl->tuned_schedule;
+            ctx->last_pipeline = pl->tuned_pipeline;
+        }
     }
     if (rc == CA_OK && schedule_out)
         *schedule_out = pl->tuned_schedule;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int ca_get_last_autotune(ca_ctx *ctx, int32_t *schedule, int32_t *pipeline)
+{
+    if (!ctx || !schedule || !pipeline)
+        return CA_E_INVAL;
+    *schedule = ctx->last_schedule;
+    *pipeline = ctx->last_pipeline;
+    return CA_OK;
 }
 
 int ca_get_tuning(ca_ctx *ctx, int32_t W, int32_t H, int32_t n_h, int32_t n_v, int32_t *out)
@@ -1340,7 +1371,7 @@ int ca_set_option(ca_ctx *ctx, int32_t option, int64_t value)
         ctx->spin_limit = value;
         return CA_OK;
     case CA_OPT_PIPELINE:
-        if (value < 1 || value > 1024)
+        if (value < 0 || value > 1024)
             return CA_E_INVAL;
         ctx->pipeline = value;
         return CA_OK;

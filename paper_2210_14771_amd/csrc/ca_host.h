@@ -43,6 +43,7 @@ struct Plan {
     std::vector<Shape> shapes;  // distinct frame shapes; shape k's strips at table k * S
     bool dynamic = false;       // a serving plan: descriptors rewritten per batch, not cached
     int32_t tuned_schedule = -1; // faster schedule of this batch (ca_autotune), -1 untuned
+    int32_t tuned_pipeline = 1;  // sub-batches of its split calls (ca_autotune)
     // launch facts
     int32_t n_frames = 0, P = 0, groups = 0, sg_len = 0, line_pitch = 0;
     int32_t rec_groups = 0;     // attempt-group records per frame the block holds (16 lanes)
@@ -91,7 +92,9 @@ struct ca_ctx {
     int64_t queues = 0;         // 0: 8 when the batch has >= 16 frames, else 1
     int64_t grid = 0;           // 0: resident workgroups from the occupancy query
     int64_t spin_limit = 1 << 20;
-    int64_t pipeline = 1;       // sub-batches of a split-schedule call (1: no side streams)
+    int64_t pipeline = 0;       // sub-batches of a split-schedule call (1: no side streams;
+                                // 0: the batch's autotuned count under CA_SCHEDULE_AUTO, else 1)
+    int32_t last_schedule = -1, last_pipeline = 0;  // what the last ca_autotune chose
     int n_cu = 0;
     // side streams of the pipelined split schedule, with their fork/join events
     hipStream_t side[2] = {nullptr, nullptr};

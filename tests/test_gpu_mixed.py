@@ -76,16 +76,19 @@ def test_graph_with_autotuned_tiles_matches_oracle(torch_dev, batch, oracle_out)
     est.set_option("strips_per_group", 0)
     say("autotuning")
     tuned = est.autotune(views, params, uids, reps=3)
-    say(f"tuned strip items per workgroup: {tuned}, schedule {est.last_tuned_schedule}")
+    say(f"tuned strip items per workgroup: {tuned}, schedule {est.last_tuned_schedule}, "
+        f"sub-batches {est.last_tuned_pipeline}")
     assert est.last_tuned_schedule in ("split", "fused")
+    assert est.last_tuned_pipeline in ((1, 2, 4) if est.last_tuned_schedule == "split" else (None,))
     assert est.get_option("schedule") == 2            # auto: the graph takes the tuned one
     assert set(tuned) == {(w, h) for w, h, _ in synth.MIXED_SHAPES}
     assert all(t in (1, 2, 4, 8) for t in tuned.values())
     out = torch.empty((N, 8), dtype=torch.int32, device="cuda")
-    # the split schedule with the tuned tiles (one strip launch per frame
-    # shape), then the persistent one (one kernel drawing strip and RANSAC
-    # work items from per-XCD queues), each captured as one graph
-    for sched in ("split", "fused"):
+    # the tuned configuration (schedule and sub-batches), the split schedule
+    # with the tuned tiles (one strip launch per frame shape), then the
+    # persistent one (one kernel drawing strip and RANSAC work items from
+    # per-XCD queues), each captured as one graph
+    for sched in ("auto", "split", "fused"):
         est.set_option("schedule", sched)
         g = est.capture(views, params, uids, out=out)
         for rep in range(2):
