@@ -3,8 +3,8 @@
 One step = one call of the whole hot path (strip scoring, candidate
 selection, RANSAC with refits, best-circle selection) on a batch of 64
 synthetic 1920x1080 RGB frames already resident in HBM.  The timed steps
-replay captured HIP graphs with four batches in flight (four contexts on
-four HIP streams taking turns, so one batch's FP64 RANSAC overlaps other
+replay captured HIP graphs with six batches in flight (six contexts on
+six HIP streams taking turns, so one batch's FP64 RANSAC overlaps other
 batches' strip loads, and the strip loads of several batches together keep
 more DRAM pages busy); the same steps with one batch in flight, and eager
 calls, are reported beside.  Prints one JSON
@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU work of the oracle sample")
-    ap.add_argument("--batches", type=int, default=5,
+    ap.add_argument("--batches", type=int, default=7,
                     help="distinct resident batches rotated (more than --inflight, so calls in "
                          "flight together read different batches)")
     ap.add_argument("--schedule", choices=["auto", "fused", "split"], default="auto",
@@ -49,7 +49,7 @@ def parse():
                          "the batch")
     ap.add_argument("--graph-calls", type=int, default=10,
                     help="estimate calls captured per HIP graph in the timed region")
-    ap.add_argument("--inflight", type=int, default=4,
+    ap.add_argument("--inflight", type=int, default=6,
                     help="batches in flight in the timed region: contexts, each with its own "
                          "plan buffers, output and HIP stream, taking the graphs in turn")
     ap.add_argument("--pipeline", type=int, default=None, help="sub-batches per split call")
@@ -81,6 +81,17 @@ def graph_calls(steps: int, wanted: int, cycle: int) -> int:
     for g in range(min(wanted, steps), 0, -1):
         if steps % g == 0 and steps // g >= cycle:
             return g
+    return 1
+
+
+def contexts_in_flight(steps: int, wanted: int, graph_max: int, min_graph: int = 4) -> int:
+    """Contexts for a timed region of `steps` calls: the most, up to `wanted`,
+    whose graphs (graph_calls) still hold at least `min_graph` calls, so short
+    runs trade a context for fewer graph launches (at 20 steps: 5 contexts
+    with 4-call graphs rather than 6 with 2-call ones)."""
+    for c in range(max(1, wanted), 1, -1):
+        if steps >= c and graph_calls(steps, graph_max, c) >= min(min_graph, steps // c):
+            return c
     return 1
 
 
@@ -183,9 +194,9 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
         est.estimate_area(resident[i % len(resident)], lp_nofb, uids, out=out)
     torch.cuda.synchronize()
     kt = est.profile_end()
-    # as in the headline step: `args.inflight` contexts (each with the model,
-    # its own buffers, output and stream) take the graph launches in turn
-    n_inflight = max(1, args.inflight)
+    # as in the headline step: up to `args.inflight` contexts (each with the
+    # model, its own buffers, output and stream) take the graph launches in turn
+    n_inflight = contexts_in_flight(K, args.inflight, 10)
     G = graph_calls(K, 10, n_inflight)
     extra = []
     for _ in range(n_inflight - 1):
@@ -606,7 +617,7 @@ def main():
     # and HIP stream) takes the graphs in turn, so one batch's RANSAC (FP64
     # ALU) overlaps the next one's strip loads (HBM); every batch still runs
     # the whole path.
-    n_inflight = max(1, args.inflight)
+    n_inflight = contexts_in_flight(K, args.inflight, args.graph_calls)
     G = graph_calls(K, args.graph_calls, n_inflight)
     extra = [make_estimator()[0] for _ in range(n_inflight - 1)]
     ests = [est] + extra

@@ -11,7 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB_PATH = os.path.join(OUT_DIR, "libcontentarea.so")
-SOURCES = ["ca_api.cpp", "ca_server.cpp", "ca_kernels.hip", "ca_cnn.hip", "ca_cnn2d.hip", "ca_noalloc.hip"]
+SOURCES = ["ca_api.cpp", "ca_server.cpp", "ca_kernels.hip", "ca_ingest.hip", "ca_cnn.hip",
+           "ca_cnn2d.hip", "ca_noalloc.hip"]
 # the device renderer of synthetic frames: an input generator, built apart
 SYNTH_LIB_PATH = os.path.join(OUT_DIR, "libcasynth.so")
 SYNTH_SOURCES = ["synth_gpu.hip"]

@@ -127,4 +127,21 @@ hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, flo
                            hipStream_t s);
 hipError_t fused_occupancy(size_t lds_bytes, int *blocks_per_cu);
 
+// Serving: the frame copies of one step into ring slots, in one launch.
+// Frame i: `rows` rows of `width` bytes from src (rows `spitch` apart) to
+// dst (rows contiguous).  Passed by value (kernel arguments), so the host
+// array may be reused as soon as the launch returns.
+struct IngestCopy {
+    const uint8_t *src;
+    uint8_t *dst;
+    int64_t spitch;
+    int32_t width, rows;
+};
+constexpr int kMaxIngest = 64;   // copies per launch
+struct IngestArgs {
+    IngestCopy c[kMaxIngest];
+    int32_t n;
+};
+hipError_t launch_ingest(const IngestArgs &a, hipStream_t s);
+
 }  // namespace ca

@@ -307,8 +307,29 @@ void admit(ca_server *s)
         s->waiting.pop_front();
 }
 
+// Copies of submitted frames into free ring slots: frames in device memory
+// go into one batched copy launch per kMaxIngest frames (k_ingest; a lone
+// frame takes the runtime's 2-D copy, measured quicker for one frame),
+// frames in host memory into one 2-D copy each.
 int ingest(ca_server *s)
 {
+    ca::IngestArgs batch;
+    batch.n = 0;
+    auto flush = [&]() {
+        if (batch.n == 0)
+            return true;
+        bool ok;
+        if (batch.n == 1) {
+            const ca::IngestCopy &c = batch.c[0];
+            ok = hipMemcpy2DAsync(c.dst, (size_t)c.width, c.src, (size_t)c.spitch, (size_t)c.width,
+                                  (size_t)c.rows, hipMemcpyDeviceToDevice, s->compute)
+                 == hipSuccess;
+        } else {
+            ok = ca::launch_ingest(batch, s->compute) == hipSuccess;
+        }
+        batch.n = 0;
+        return ok;
+    };
     for (Stream *st : s->order) {
         if (!st->admitted)
             continue;
@@ -318,16 +339,25 @@ int ingest(ca_server *s)
             const int32_t slot = st->free_slots.back();
             st->free_slots.pop_back();
             uint8_t *dst = s->arena_mem + st->ring_off + (size_t)slot * st->slot_bytes;
-            if (hipMemcpy2DAsync(dst, (size_t)3 * st->W, p.src, (size_t)p.stride,
-                                 (size_t)3 * st->W, (size_t)st->H,
-                                 p.is_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                 s->compute) != hipSuccess)
+            if (p.is_dev) {
+                ca::IngestCopy &c = batch.c[batch.n++];
+                c.src = p.src;
+                c.dst = dst;
+                c.spitch = p.stride;
+                c.width = 3 * st->W;
+                c.rows = st->H;
+                if (batch.n == ca::kMaxIngest && !flush())
+                    return CA_E_DEVICE;
+            } else if (hipMemcpy2DAsync(dst, (size_t)3 * st->W, p.src, (size_t)p.stride,
+                                        (size_t)3 * st->W, (size_t)st->H, hipMemcpyHostToDevice,
+                                        s->compute) != hipSuccess) {
                 return CA_E_DEVICE;
+            }
             s->ready.push_back({st, p.seq, slot, p.t_submit});
             ++st->outstanding;
         }
     }
-    return CA_OK;
+    return flush() ? CA_OK : CA_E_DEVICE;
 }
 
 int launch(ca_server *s)

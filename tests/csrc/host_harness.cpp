@@ -453,6 +453,21 @@ hipError_t launch_stream_update(const ca_result *res, const int4 *runs, int n_ru
     }
     return hipSuccess;
 }
+hipError_t launch_ingest(const IngestArgs &a, hipStream_t)
+{
+    ++g_async_ops;
+    if (a.n < 1 || a.n > kMaxIngest)
+        fail("ingest launch %s", "with a bad copy count");
+    for (int i = 0; i < a.n; ++i) {
+        const IngestCopy &c = a.c[i];
+        if (c.width < 1 || c.rows < 1 || c.spitch < c.width)
+            fail("ingest copy %s", "with a bad shape");
+        check_device(c.dst, (size_t)c.width * (size_t)c.rows, "ingest destination");
+        check_device(c.src, (size_t)c.spitch * (size_t)(c.rows - 1) + (size_t)c.width,
+                     "ingest source");
+    }
+    return hipSuccess;
+}
 hipError_t launch_fallback(ca_result *out, const ca_result *fallback, int n, float, hipStream_t)
 {
     ++g_async_ops;

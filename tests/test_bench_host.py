@@ -109,3 +109,15 @@ def test_strip_kernel_name_follows_the_pairing_rule():
     assert bench.strip_kernel(16, 0) == "k_strips_pair"
     assert bench.strip_kernel(32, 31) == "k_strips"
     assert bench.strip_kernel(32, 32, tiles=2) == "k_strips"
+
+
+def test_contexts_in_flight_keep_graphs_of_four_calls():
+    # 1000 steps: six contexts with 10-call graphs; 20 steps: five with 4-call
+    # graphs rather than six with 2-call ones; every context always runs
+    assert bench.contexts_in_flight(1000, 6, 10) == 6
+    assert bench.contexts_in_flight(20, 6, 10) == 5
+    assert bench.graph_calls(20, 10, 5) == 4
+    for steps in (1, 3, 5, 7, 20, 33, 100):
+        c = bench.contexts_in_flight(steps, 6, 10)
+        assert 1 <= c <= min(6, steps)
+        assert steps // bench.graph_calls(steps, 10, c) >= c
