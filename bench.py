@@ -698,7 +698,7 @@ def main():
         strips_ms = kt["strips"]["avg_ms"]
         ransac_ms = kt["ransac"]["avg_ms"]
         kernels = {"k_" + k: {"avg_us": v["avg_ms"] * 1e3, "launches": v["launches"]}
-                   for k, v in kt.items() if k != "unused"}
+                   for k, v in kt.items() if k != "gap"}
         dominant = "strips" if strips_ms >= ransac_ms else "ransac"
     skern = strip_kernel(kw["n_hstrips"], kw["n_vstrips"], max(tiles.values(), default=1))
     if schedule_used != "fused" and "k_strips" in kernels:

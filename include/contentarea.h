@@ -437,10 +437,12 @@ int ca_get_option(ca_ctx *ctx, int32_t option, int64_t *value);
  * the flag. */
 int ca_device_status(ca_ctx *ctx);
 
-/* Kernel timing (HIP events recorded on the caller's stream around each
- * kernel of each call).  Index 0: strip scoring, 1: RANSAC with selection,
- * 2: unused.  When a call is one fused kernel or a pipelined set of
- * sub-batches, the whole call is reported at index 0. */
+/* Kernel timing (HIP events taken by each kernel's own dispatch, so each
+ * duration is the kernel's execution alone).  Index 0: strip scoring, 1:
+ * RANSAC with selection, 2: the gap between them.  When a call is one fused
+ * kernel it is reported at index 0; a pipelined set of sub-batches, or the
+ * per-shape strip launches of a mixed batch, between marker events recorded
+ * on the caller's stream. */
 typedef struct {
     double total_ms[3];      /* summed kernel durations */
     int64_t launches[3];     /* number of timed launches */

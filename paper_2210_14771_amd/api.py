@@ -370,7 +370,7 @@ class Estimator:
         """Average kernel durations (ms) of the calls timed since profile_begin."""
         t = N.KernelTimes()
         N.check(N.lib().ca_profile_end(self._ctx, C.byref(t)), "ca_profile_end")
-        names = ("strips", "ransac", "unused")
+        names = ("strips", "ransac", "gap")
         return {n: {"total_ms": t.total_ms[i], "launches": int(t.launches[i]),
                     "avg_ms": t.total_ms[i] / t.launches[i] if t.launches[i] else 0.0}
                 for i, n in enumerate(names)}

@@ -453,10 +453,9 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
         int grid = ctx->grid > 0 ? (int)ctx->grid : pl->fused_grid;
         grid = (grid + fa.nq - 1) / fa.nq * fa.nq;  // equal workgroups per queue
         // the whole call is one kernel: it is timed as the strip-scoring slot
-        if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
-            || ca::launch_fused(fa, grid, pl->fused_lds, s) != hipSuccess
-            || (ev && (hipEventRecord(ev[1], s) != hipSuccess || hipEventRecord(ev[2], s) != hipSuccess
-                       || hipEventRecord(ev[3], s) != hipSuccess)))
+        if (ca::launch_fused(fa, grid, pl->fused_lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr)
+                != hipSuccess
+            || (ev && (hipEventRecord(ev[2], s) != hipSuccess || hipEventRecord(ev[3], s) != hipSuccess)))
             return CA_E_DEVICE;
         return CA_OK;
     }
@@ -464,7 +463,12 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
     const int S = p.n_hstrips + p.n_vstrips;
     const bool learned = p.scorer == CA_SCORER_LEARNED;
     const bool learned2d = p.scorer == CA_SCORER_LEARNED_2D;
-    auto launch_range = [&](int32_t f0, int32_t f1, hipStream_t st, hipEvent_t mid) {
+    // tev (timed calls): the strip kernel between tev[0] and tev[1], RANSAC
+    // between tev[2] and tev[3], each pair taken by the dispatch itself (the
+    // per-shape strip launches of a mixed batch between two marker events)
+    auto launch_range = [&](int32_t f0, int32_t f1, hipStream_t st, hipEvent_t *tev) {
+        hipEvent_t s0 = tev ? tev[0] : nullptr, s1 = tev ? tev[1] : nullptr;
+        hipEvent_t r0 = tev ? tev[2] : nullptr, r1 = tev ? tev[3] : nullptr;
         ca::StripArgs a2 = sa;
         a2.frame0 = f0;
         a2.n_items = (f1 - f0) * S;
@@ -484,7 +488,7 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
             c.n_items = a2.n_items;
             c.per_xcd = a2.per_xcd;
             c.frame0 = f0;
-            ok = ca::launch_cnn2d_strips(c, st) == hipSuccess;
+            ok = ca::launch_cnn2d_strips(c, st, s0, s1) == hipSuccess;
         } else if (learned) {
             ca::CnnStripArgs c;
             c.frames = frames;
@@ -500,32 +504,28 @@ int enqueue_one(ca_ctx *ctx, Plan *pl, const uint8_t *frames, int32_t n, const c
             if (ctx->cnn_groups_per_xcd == 0)
                 ctx->cnn_groups_per_xcd =
                     std::max(1, (ctx->n_cu > 0 ? ctx->n_cu : 256) / 8 * ca::cnn_strips_blocks_per_cu());
-            ok = ca::launch_cnn_strips(c, std::min(c.per_xcd, ctx->cnn_groups_per_xcd), st)
+            ok = ca::launch_cnn_strips(c, std::min(c.per_xcd, ctx->cnn_groups_per_xcd), st, s0, s1)
                  == hipSuccess;
         } else if (f0 == 0 && f1 == n && !pl->dynamic
                    && (pl->classes.size() > 1
                        || strips_per_group(ctx, pl->classes[0].W, pl->classes[0].H, p) != 1)) {
             // the whole batch: one launch per frame shape, each with its tile
-            ok = true;
+            ok = !s0 || hipEventRecord(s0, st) == hipSuccess;
             for (const Plan::ShapeClass &c : pl->classes)
                 ok = ok
                      && launch_class_strips(sa, pl, c, strips_per_group(ctx, c.W, c.H, p), S, st)
                             == hipSuccess;
+            ok = ok && (!s1 || hipEventRecord(s1, st) == hipSuccess);
         } else {
-            ok = ca::launch_strips(a2, pl->lds, st) == hipSuccess;
+            ok = ca::launch_strips(a2, pl->lds, st, s0, s1) == hipSuccess;
         }
-        return ok && (!mid || hipEventRecord(mid, st) == hipSuccess)
-               && ca::launch_ransac(r2, se, f1 - f0, st) == hipSuccess;
+        return ok && ca::launch_ransac(r2, se, f1 - f0, st, r0, r1) == hipSuccess;
     };
     const int64_t want = ctx->pipeline > 0 ? ctx->pipeline
                          : (ctx->schedule == CA_SCHEDULE_AUTO ? pl->tuned_pipeline : 1);
     const int32_t nsub = want > 1 ? (int32_t)std::min<int64_t>(want, n) : 1;
     if (nsub == 1) {
-        if ((ev && hipEventRecord(ev[0], s) != hipSuccess)
-            || !launch_range(0, n, s, ev ? ev[1] : nullptr)
-            || (ev && (hipEventRecord(ev[2], s) != hipSuccess || hipEventRecord(ev[3], s) != hipSuccess)))
-            return CA_E_DEVICE;
-        return CA_OK;
+        return launch_range(0, n, s, ev) ? CA_OK : CA_E_DEVICE;
     }
     // sub-batches alternate over two side streams, forked from and joined
     // back into the caller's stream: one sub-batch's RANSAC (ALU bound)
@@ -775,9 +775,12 @@ int ca_profile_end(ca_ctx *ctx, ca_kernel_times *out)
             rc = CA_E_DEVICE;
             break;
         }
+        // slots: strip kernel(s) ev0 -> ev1, RANSAC ev2 -> ev3, and the gap
+        // between them ev1 -> ev2
+        const int from[3] = {0, 2, 1}, to[3] = {1, 3, 2};
         for (int k = 0; k < 3; ++k) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) {
+            if (hipEventElapsedTime(&ms, ev[from[k]], ev[to[k]]) != hipSuccess) {
                 rc = CA_E_DEVICE;
                 break;
             }

@@ -74,7 +74,8 @@ hipError_t launch_cnn_windows(const uint8_t *model, const uint8_t *win, const in
                               float *z, int n, hipStream_t s);
 // Learned candidates; a.per_xcd = items per XCD slice, groups_per_xcd =
 // workgroups per XCD (each takes the slice's items in turn).
-hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s);
+hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s,
+                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Resident workgroups of k_cnn_strips per compute unit.
 int cnn_strips_blocks_per_cu();
 
@@ -138,7 +139,8 @@ struct Cnn2dTrainArgs {
     int32_t n;
 };
 
-hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t s);
+hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t s, hipEvent_t start = nullptr,
+                               hipEvent_t stop = nullptr);
 hipError_t launch_cnn2d_windows(const uint8_t *model, const uint8_t *win, const int32_t *geom,
                                 const int32_t *range, float *z, int n, hipStream_t s);
 hipError_t launch_cnn2d_grad(const Cnn2dTrainArgs &a, int grid, hipStream_t s);

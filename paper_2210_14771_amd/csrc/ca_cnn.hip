@@ -19,6 +19,7 @@
 // multiple of 32 with zeros), B = activations, 16 output channels x 16
 // positions per tile.
 #include "ca_cnn.h"
+#include "ca_launch.h"
 
 namespace ca {
 namespace {
@@ -1014,12 +1015,13 @@ int cnn_strips_blocks_per_cu()
     return b;
 }
 
-hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s)
+hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t s,
+                             hipEvent_t start, hipEvent_t stop)
 {
     if (a.n_items <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_cnn_strips, dim3(8 * groups_per_xcd), dim3(kCnnWaveBlock), kCnnWaveLds, s,
-                       a);
+    launch_maybe_timed(k_cnn_strips, dim3(8 * groups_per_xcd), dim3(kCnnWaveBlock), kCnnWaveLds, s,
+                       start, stop, a);
     return hipGetLastError();
 }
 

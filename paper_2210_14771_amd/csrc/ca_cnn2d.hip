@@ -20,6 +20,7 @@
 // ("same" zero padding of the whole-image network).  Weights and hidden
 // activations are bfloat16, sums are float32 MFMA accumulators.
 #include "ca_cnn.h"
+#include "ca_launch.h"
 
 namespace ca {
 namespace {
@@ -1016,11 +1017,12 @@ __global__ __launch_bounds__(kBlock) void k_cnn2d_pack(const float *master, uint
 
 }  // namespace
 
-hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t s)
+hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t s, hipEvent_t start,
+                               hipEvent_t stop)
 {
     if (a.n_items <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_cnn2d_strips, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, a);
+    launch_maybe_timed(k_cnn2d_strips, dim3(8 * a.per_xcd), dim3(kBlock), 0, s, start, stop, a);
     return hipGetLastError();
 }
 

@@ -113,9 +113,13 @@ struct FusedArgs {
 
 size_t strip_lds_bytes(int sg_len, int line_pitch);
 size_t fused_lds_bytes(int sg_len, int line_pitch);
-hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s);
-hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s);
-hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s);
+// start/stop (optional): events the dispatch itself records around the kernel
+hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s,
+                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s,
+                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s,
+                        hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Serving: fold each run of a batch's results (one stream's frames, in
 // sequence order: run = (state index, first, end)) into the stream's
 // filtered circle (cx, cy, r, weight); filt[i] = the state after frame i.

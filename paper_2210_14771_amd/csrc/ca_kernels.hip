@@ -32,6 +32,7 @@
 // arithmetic without contraction (build with -ffp-contract=off), integer
 // inlier moments (summed here in float64, exact below 2^53).
 #include "ca_internal.h"
+#include "ca_launch.h"
 
 namespace ca {
 namespace {
@@ -1178,7 +1179,8 @@ size_t fused_lds_bytes(int sg_len, int line_pitch)
     return (size_t)(sg_len + kQtBins + kLumaLevels) * sizeof(float) + 16 + work;
 }
 
-hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s)
+hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s, hipEvent_t start,
+                         hipEvent_t stop)
 {
     if (a.n_items <= 0)
         return hipSuccess;
@@ -1189,30 +1191,32 @@ hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t s)
         StripArgs p = a;
         p.n_items = a.n_items / 2;
         p.per_xcd = (p.n_items + 7) / 8;
-        hipLaunchKernelGGL(k_strips_pair, dim3(8 * p.per_xcd), dim3(2 * kBlock), pair_lds, s, p);
+        launch_maybe_timed(k_strips_pair, dim3(8 * p.per_xcd), dim3(2 * kBlock), pair_lds, s, start,
+                           stop, p);
         return hipGetLastError();
     }
-    const dim3 grid(8 * a.per_xcd);
-    hipLaunchKernelGGL(k_strips, grid, dim3(kBlock), lds_bytes, s, a);
+    launch_maybe_timed(k_strips, dim3(8 * a.per_xcd), dim3(kBlock), lds_bytes, s, start, stop, a);
     return hipGetLastError();
 }
 
-hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s)
+hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t s,
+                         hipEvent_t start, hipEvent_t stop)
 {
     if (n_frames <= 0)
         return hipSuccess;
+    const dim3 grid(a.groups, n_frames);
     switch (a.lanes) {
     case 2:
-        hipLaunchKernelGGL(k_ransac<2>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        launch_maybe_timed(k_ransac<2>, grid, dim3(kBlock), 0, s, start, stop, a, sel);
         break;
     case 4:
-        hipLaunchKernelGGL(k_ransac<4>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        launch_maybe_timed(k_ransac<4>, grid, dim3(kBlock), 0, s, start, stop, a, sel);
         break;
     case 8:
-        hipLaunchKernelGGL(k_ransac<8>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        launch_maybe_timed(k_ransac<8>, grid, dim3(kBlock), 0, s, start, stop, a, sel);
         break;
     case 16:
-        hipLaunchKernelGGL(k_ransac<16>, dim3(a.groups, n_frames), dim3(kBlock), 0, s, a, sel);
+        launch_maybe_timed(k_ransac<16>, grid, dim3(kBlock), 0, s, start, stop, a, sel);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1220,11 +1224,12 @@ hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frame
     return hipGetLastError();
 }
 
-hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s)
+hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t s,
+                        hipEvent_t start, hipEvent_t stop)
 {
     if (a.se.n_frames <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kBlock), lds_bytes, s, a);
+    launch_maybe_timed(k_fused, dim3(grid), dim3(kBlock), lds_bytes, s, start, stop, a);
     return hipGetLastError();
 }
 

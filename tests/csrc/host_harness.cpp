@@ -394,7 +394,7 @@ size_t strip_lds_bytes(int sg_len, int line_pitch)
 }
 size_t fused_lds_bytes(int sg_len, int line_pitch) { return strip_lds_bytes(sg_len, line_pitch) + 4096; }
 
-hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t)
+hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t, hipEvent_t, hipEvent_t)
 {
     ++g_async_ops;
     const int32_t S = a.n_h + a.n_v;
@@ -408,7 +408,8 @@ hipError_t launch_strips(const StripArgs &a, size_t lds_bytes, hipStream_t)
     }
     return hipSuccess;
 }
-hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t)
+hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frames, hipStream_t,
+                         hipEvent_t, hipEvent_t)
 {
     ++g_async_ops;
     check_device(a.cand + (size_t)a.frame0 * a.P, sizeof(ca_point) * (size_t)n_frames * a.P,
@@ -423,7 +424,8 @@ hipError_t launch_ransac(const RansacArgs &a, const SelectArgs &sel, int n_frame
     write_results(sel.out, a.frame0, n_frames);
     return hipSuccess;
 }
-hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t)
+hipError_t launch_fused(const FusedArgs &a, int grid, size_t lds_bytes, hipStream_t, hipEvent_t,
+                        hipEvent_t)
 {
     ++g_async_ops;
     if (grid < 1 || lds_bytes < fused_lds_bytes(a.s.sg_len, a.s.line_pitch))
@@ -480,7 +482,8 @@ hipError_t fused_occupancy(size_t, int *blocks_per_cu)
     *blocks_per_cu = 2;
     return hipSuccess;
 }
-hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t)
+hipError_t launch_cnn_strips(const CnnStripArgs &a, int groups_per_xcd, hipStream_t, hipEvent_t,
+                             hipEvent_t)
 {
     ++g_async_ops;
     if (groups_per_xcd < 1)
@@ -499,7 +502,7 @@ hipError_t launch_cnn_update(float *, float *, const float *, float, float, uint
 }
 hipError_t launch_cnn_pack(const float *, uint8_t *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mfma_probe(float *, hipStream_t) { return hipSuccess; }
-hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t)
+hipError_t launch_cnn2d_strips(const Cnn2dStripArgs &a, hipStream_t, hipEvent_t, hipEvent_t)
 {
     ++g_async_ops;
     const int32_t S = a.n_h + a.n_v;
