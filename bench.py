@@ -188,12 +188,14 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     for i in range(5):
         est.estimate_area(resident[i % len(resident)], lp, uids, out=out)
     torch.cuda.synchronize()
+    saved_pipeline = est.get_option("pipeline")
     est.set_option("pipeline", 1)
     est.profile_begin(K)
     for i in range(K):
         est.estimate_area(resident[i % len(resident)], lp_nofb, uids, out=out)
     torch.cuda.synchronize()
     kt = est.profile_end()
+    est.set_option("pipeline", saved_pipeline)
     # as in the headline step: up to `args.inflight` contexts (each with the
     # model, its own buffers, output and stream) take the graph launches in turn
     n_inflight = contexts_in_flight(K, args.inflight, 10)

@@ -409,7 +409,9 @@ void ca_graph_destroy(ca_graph *graph);
  * Then (handcrafted scorer) it times `reps` whole calls of the batch under
  * the split schedule with those tiles, in one call and in 2 and 4 pipelined
  * sub-batches (CA_OPT_PIPELINE), and under the persistent fused schedule,
- * and keeps the fastest for this batch (used with CA_SCHEDULE_AUTO and the
+ * each both eagerly and as a replayed one-call graph (a candidate counts by
+ * the slower of the two), and keeps the fastest for this batch (used with
+ * CA_SCHEDULE_AUTO and the
  * pipeline option at 0); *schedule_out (may be NULL) receives its schedule,
  * ca_get_last_autotune the schedule and sub-batch count.  Later calls (and
  * graphs captured later) use the results.  Blocking.  Results never depend

@@ -1279,7 +1279,35 @@ int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, i
     // whole calls of this batch: the split schedule (with the tiles just
     // chosen) in one call or cut into 2 or 4 pipelined sub-batches, against
     // the persistent one; the fastest serves CA_SCHEDULE_AUTO (with the
-    // pipeline option at 0)
+    // pipeline option at 0).  Each is timed eagerly and replayed from a
+    // captured one-call graph, and counts by the slower of the two (the
+    // side streams of the pipelined calls overlap differently in the two
+    // forms), so the choice holds for eager callers and graph users alike.
+    auto time_graph = [&](float *ms) {
+        hipStream_t cs = nullptr;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            return false;
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const bool enq =
+                enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, cs, false) == CA_OK;
+            ok = hipStreamEndCapture(cs, &gr) == hipSuccess && gr && enq
+                 && hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+        }
+        ok = ok && hipGraphLaunch(ex, st) == hipSuccess && hipEventRecord(e0, st) == hipSuccess;
+        for (int32_t r = 0; ok && r < reps; ++r)
+            ok = hipGraphLaunch(ex, st) == hipSuccess;
+        ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess
+             && hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+        if (ex)
+            (void)hipGraphExecDestroy(ex);
+        if (gr)
+            (void)hipGraphDestroy(gr);
+        (void)hipStreamDestroy(cs);
+        return ok;
+    };
     if (rc == CA_OK && p.scorer == CA_SCORER_HANDCRAFTED) {
         const int64_t saved_schedule = ctx->schedule, saved_pipeline = ctx->pipeline;
         struct Trial {
@@ -1298,9 +1326,10 @@ int ca_autotune(ca_ctx *ctx, const uint8_t *frames, const ca_frame_desc *dims, i
                       && hipEventRecord(e0, st) == hipSuccess;
             for (int32_t r = 0; ok && r < reps; ++r)
                 ok = enqueue(ctx, pl, frames, n, p, nullptr, nullptr, pl->res2, st, false) == CA_OK;
-            float ms = 0.0f;
+            float ms = 0.0f, ms_graph = 0.0f;
             ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess
-                 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                 && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && time_graph(&ms_graph);
+            ms = ms > ms_graph ? ms : ms_graph;
             if (!ok)
                 rc = CA_E_DEVICE;
             else if (k == 0 || ms < best_ms) {
