@@ -168,3 +168,49 @@ def test_streams_wait_for_memory(torch_dev, streams):
     assert st_["streams_waiting"] == 0 and st_["streams_admitted"] == 2
     srv.close()
     est.close()
+
+
+def test_strided_and_contiguous_frames_in_one_backlog(torch_dev, streams):
+    """Frames with padded rows (views into wider images) and contiguous ones
+    submitted together as a backlog: the step's batched copy into ring slots
+    takes the byte path for the first and the 16-byte path for the second;
+    every result equals the batch API's on the same frame and uid."""
+    torch = torch_dev
+    est = api.Estimator(0)
+    srv = serve.Server(est, serve.server_config(max_batch=16, **KW))
+    src = [streams[0], streams[1]]                     # 720p and 1080p
+    ids = [100, 101, 102, 103]
+    frames = {}
+    for k, sid in enumerate(ids):
+        st = src[k % 2]
+        base = st.frames[0]
+        if k < 2:                                      # padded rows: a view into a wider image
+            wide = torch.zeros((st.height, st.width + 7, 3), dtype=torch.uint8, device="cuda")
+            wide[:, :st.width].copy_(base)
+            f = wide[:, :st.width]
+            assert f.stride(0) == 3 * (st.width + 7)
+        else:
+            f = base
+        frames[sid] = (f, st)
+        assert srv.open(sid, st.width, st.height)
+    torch.cuda.synchronize()
+    for seq in range(3):
+        for sid in ids:
+            srv.submit(sid, seq, frames[sid][0])
+    served = []
+    for _ in range(100000):
+        served += [serve.served_record(s) for s in srv.step()]
+        if len(served) == 3 * len(ids):
+            break
+    assert len(served) == 3 * len(ids)
+    assert max(r["batch"] for r in served) > 1          # several frames per step
+    for r in served:
+        f, _ = frames[r["stream"]]
+        uid = (r["stream"] << 32) | r["seq"]
+        res = est.estimate_area(f, api.default_params(**KW), [uid])
+        torch.cuda.synchronize()
+        raw = res.raw.cpu().numpy()[0]
+        want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
+        assert r["result"] == want, (r["stream"], r["seq"])
+    srv.close()
+    est.close()
