@@ -200,40 +200,50 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
     # model, its own buffers, output and stream) take the graph launches in turn
     n_inflight = contexts_in_flight(K, args.inflight, 10)
     G = graph_calls(K, 10, n_inflight)
-    extra = []
-    for _ in range(n_inflight - 1):
-        e = api.Estimator(0)
-        e.set_model(train_scorer.load_model(path))
-        extra.append(e)
-    ests = [est] + extra
-    outs = [out] + [torch.empty_like(out) for _ in extra]
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in extra]
-    used = {}
 
-    def graph_region(n):
-        graphs = [[ests[k].capture(r, lp, uids, out=outs[k], calls=G) for r in resident]
-                  for k in range(n)]
-        for k in range(n):
-            for g in graphs[k]:
-                g.launch(streams[k])
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for i in range(K // G):
-            graphs[i % n][i % len(resident)].launch(streams[i % n])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        for gs in graphs:
-            for g in gs:
-                g.close()
-        used[n] = rotation_used(K // G, n, len(resident))
-        return dt
+    def inflight_timing(params, load_model):
+        """Elapsed time of K calls with one context, then with n_inflight
+        (graphs of G calls taken in turn), the rotation each touched, and
+        whether every context gives the first one's results."""
+        extra = []
+        for _ in range(n_inflight - 1):
+            e = api.Estimator(0)
+            load_model(e)
+            extra.append(e)
+        ests = [est] + extra
+        outs = [out] + [torch.empty_like(out) for _ in extra]
+        streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in extra]
+        used = {}
 
-    elapsed_one = graph_region(1)
-    elapsed = graph_region(n_inflight) if n_inflight > 1 else elapsed_one
-    ref = est.estimate_area(resident[0], lp, uids).raw
-    identical = all(torch.equal(e.estimate_area(resident[0], lp, uids).raw, ref) for e in extra)
-    for e in extra:
-        e.close()
+        def graph_region(n):
+            graphs = [[ests[k].capture(r, params, uids, out=outs[k], calls=G) for r in resident]
+                      for k in range(n)]
+            for k in range(n):
+                for g in graphs[k]:
+                    g.launch(streams[k])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for i in range(K // G):
+                graphs[i % n][i % len(resident)].launch(streams[i % n])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            for gs in graphs:
+                for g in gs:
+                    g.close()
+            used[n] = rotation_used(K // G, n, len(resident))
+            return dt
+
+        one = graph_region(1)
+        many = graph_region(n_inflight) if n_inflight > 1 else one
+        ref = est.estimate_area(resident[0], params, uids).raw
+        same = all(torch.equal(e.estimate_area(resident[0], params, uids).raw, ref)
+                   for e in extra)
+        for e in extra:
+            e.close()
+        return one, many, used, same
+
+    elapsed_one, elapsed, used, identical = inflight_timing(
+        lp, lambda e: e.set_model(train_scorer.load_model(path)))
     lat = []
     for i in range(min(args.latency_calls, 100)):
         t1 = time.perf_counter()
@@ -266,36 +276,33 @@ def learned_section(args, est, resident, specs, params_plain, kw, uids, out):
             acc[name]["learned_2d_fallback"] = evaluate.accuracy(est, fr, sp, lp2, by=True)
     learned_2d = None
     if has2d:
-        # the paper's own network: kernel time (library events) and whole-call
-        # throughput from graph replays, one batch in flight
+        # the paper's own network: kernel time (dispatch events) and whole-call
+        # throughput from graph replays, one and n_inflight batches in flight
         print("# learned 2-D scorer", file=sys.stderr, flush=True)
+        saved_pipeline = est.get_option("pipeline")
+        est.set_option("pipeline", 1)
         est.profile_begin(K)
         for i in range(K):
             est.estimate_area(resident[i % len(resident)], lp2_nofb, uids, out=out)
         torch.cuda.synchronize()
         kt2 = est.profile_end()
-        G2 = graph_calls(K, 10, len(resident))
-        graphs = [est.capture(r, lp2, uids, out=out, calls=G2) for r in resident]
-        for g in graphs:
-            g.launch()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for i in range(K // G2):
-            graphs[i % len(resident)].launch()
-        torch.cuda.synchronize()
-        el2 = time.perf_counter() - t
-        for g in graphs:
-            g.close()
+        est.set_option("pipeline", saved_pipeline)
+        model2d = train_scorer.load_model_2d(path2d)
+        el2_one, el2, used2, same2 = inflight_timing(lp2, lambda e: e.set_model_2d(model2d))
         ms2 = kt2["strips"]["avg_ms"]
         fl2 = B * cnn2d_flops_per_frame(W, H, kw["n_hstrips"], kw["n_vstrips"])
         rl2 = {"kernel": "k_cnn2d_strips", "bound": "mfma",
                "achieved": fl2 / (ms2 * 1e-3) / 1e12, "peak": BF16_MFMA_PEAK_TFLOPS,
                "unit": "TFLOP/s", "traffic": measured_traffic("k_cnn2d_strips", "ca_cnn2d.hip")}
         rl2["frac"] = rl2["achieved"] / rl2["peak"]
-        learned_2d = {"value": B * (K // G2) * G2 / el2, "unit": "frames/s",
-                      "ms_per_step": el2 / ((K // G2) * G2) * 1e3,
-                      "timing": f"{K // G2} launches of HIP graphs of {G2} calls, one batch in "
-                                f"flight, with the handcrafted fallback",
+        learned_2d = {"value": B * K / el2, "unit": "frames/s", "ms_per_step": el2 / K * 1e3,
+                      "timing": f"{K // G} launches of HIP graphs of {G} calls on "
+                                f"{used2[n_inflight]['contexts']} contexts taking the launches "
+                                f"in turn, over {used2[n_inflight]['batches']} distinct resident "
+                                f"batches, with the handcrafted fallback",
+                      "inflight": dict(used2[n_inflight], graph_calls=G, launches=K // G,
+                                       results_identical=bool(same2)),
+                      "one_in_flight_value": B * K / el2_one,
                       "scorer": "the paper's 2-D CNN (3x3 convolutions 8/16/32 on RGBXY bands, "
                                 "BF16 MFMA), handcrafted fallback below 0.5 inlier fraction",
                       "kernels": {"k_cnn2d_strips": {"avg_us": ms2 * 1e3},
