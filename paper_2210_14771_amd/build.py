@@ -29,6 +29,11 @@ FLAGS = [
     "-fno-fast-math",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in architectural VGPRs rather than AGPRs where the
+    # budget allows: the 2-D scorer's epilogues then read them without a
+    # v_accvgpr_read per element (measured 304-308 -> 292-295 us per 64 x
+    # 1080p launch of k_cnn2d_strips, candidates identical)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
     "-Wno-unused-command-line-argument",
 ]
