@@ -2,10 +2,10 @@
 and UndefinedBehaviorSanitizer, built with g++ against a stand-in HIP runtime
 (tests/csrc/hip_stub) and driven without a GPU by tests/csrc/host_harness.cpp:
 the batch API over mixed shapes, plan eviction, every schedule option and
-graphs; the serving loop on serve_bench's sequence (per scorer a warm-up
-server fed everything at once, then a real-time server on the same context),
-with more stream shapes than frames per batch, and with streams waiting for
-memory.  The stand-in kernels check that every frame byte, strip table and
+graphs; the serving loop fed a whole backlog at once and then in real
+time by a second server on the same context (per scorer, as the serving
+benchmark runs them, in the other order), with more stream shapes than
+frames per batch, and with streams waiting for memory.  The stand-in kernels check that every frame byte, strip table and
 output they would touch lies inside its allocation, and any synchronous
 runtime call inside ca_server_step aborts the run."""
 import os
@@ -60,8 +60,8 @@ def test_more_stream_shapes_than_batch_frames(harness):
 
 
 def test_serve_bench_sequence_never_blocks(harness):
-    # two simulated seconds of 48 streams: the length after which the
-    # real-time run once stopped making progress on the GPU
+    # two simulated seconds of 48 streams, a backlog server then a real-time
+    # one per scorer; no call inside step may block
     out = _run(harness, "serve_sequence", "2.0")
     for name in ("plain warm-up", "plain realtime", "learned warm-up", "learned realtime"):
         assert f"ok {name}" in out, name
