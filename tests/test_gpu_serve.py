@@ -214,3 +214,32 @@ def test_strided_and_contiguous_frames_in_one_backlog(torch_dev, streams):
         assert r["result"] == want, (r["stream"], r["seq"])
     srv.close()
     est.close()
+
+
+def test_learned_scorers_served_equal_the_batch_api(torch_dev, streams):
+    """Both learned scorers with the handcrafted fallback behind the server:
+    every served frame's result equals the batch API's on the same frame and
+    uid (the server runs the same kernels on its own batches)."""
+    torch = torch_dev
+    model2d = os.path.join(train_scorer.MODEL_DIR, train_scorer.MODEL_FILE_2D)
+    if not (os.path.exists(MODEL) and os.path.exists(model2d)):
+        pytest.skip("no trained scorer models")
+    est = api.Estimator(0)
+    est.set_model(train_scorer.load_model())
+    est.set_model_2d(train_scorer.load_model_2d(model2d))
+    for scorer in (1, 2):
+        kw = dict(KW, scorer=scorer, fallback_inlier_frac=0.5)
+        srv = serve.Server(est, serve.server_config(max_batch=16, **kw))
+        got, _ = serve.run(srv, streams[:4], realtime=False)
+        srv.close()
+        assert len(got) == sum(len(s.arrivals) for s in streams[:4])
+        for r in got:
+            st = streams[r["stream"]]
+            frame = st.frames[r["seq"] % len(st.frames)]
+            uid = (r["stream"] << 32) | r["seq"]
+            res = est.estimate_area(frame, api.default_params(**kw), [uid])
+            torch.cuda.synchronize()
+            raw = res.raw.cpu().numpy()[0]
+            want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
+            assert r["result"] == want, (scorer, r["stream"], r["seq"])
+    est.close()
