@@ -208,10 +208,13 @@ def test_mixed_resolutions_in_one_batch(torch_dev, est):
         assert_results_equal(g["res"][i:i + 1], [r])
 
 
-def test_odd_sizes_in_one_batch(torch_dev, est):
+@pytest.mark.parametrize("n_h,n_v", [(8, 12), (4, 3)], ids=["pairs", "single_strips"])
+def test_odd_sizes_in_one_batch(torch_dev, est, n_h, n_v):
     # 20 frames of small and odd extents (from the 16-pixel minimum, odd
     # heights, half lines of odd length, a tall narrow frame) in one batch:
-    # every candidate and result equals the oracle's
+    # every candidate and result equals the oracle's.  The strip counts take
+    # each strip kernel in turn: strips in pairs (8 + 12), one per workgroup
+    # (4 + 3: an odd count).
     torch = torch_dev
     sizes = [(16, 40), (33, 64), (63, 48), (64, 96), (65, 80), (97, 120), (129, 64), (1000, 72),
              (480, 640), (31, 200)] * 2
@@ -219,8 +222,8 @@ def test_odd_sizes_in_one_batch(torch_dev, est):
               for i, (h, w) in enumerate(sizes)]
     devs = [torch.from_numpy(f).cuda() for f in frames]
     uids = [700 + i for i in range(len(frames))]
-    kw = dict(n_hstrips=8, n_vstrips=12, ransac_attempts=64)
-    say("odd sizes in one batch")
+    kw = dict(n_hstrips=n_h, n_vstrips=n_v, ransac_attempts=64)
+    say(f"odd sizes in one batch, {n_h} + {n_v} strips")
     g = run_gpu(est, devs, kw, uids, what=("pts", "res"))
     for i, f in enumerate(frames):
         r, p = oracle.estimate(f, oracle_params(**kw), uids[i], with_points=True)
