@@ -231,6 +231,27 @@ def test_odd_sizes_in_one_batch(torch_dev, est, n_h, n_v):
         assert_results_equal(g["res"][i:i + 1], [r])
 
 
+def test_many_vertical_strips_on_odd_sizes(torch_dev, est):
+    # 40 frames of small and odd extents with 32 vertical strips (on the
+    # narrowest frames many strips share a column); under the pipelined
+    # schedules sub-batches start mid-batch.  Every candidate and result
+    # equals the oracle's
+    torch = torch_dev
+    sizes = [(16, 40), (33, 64), (63, 48), (64, 96), (65, 80), (97, 120), (129, 64), (1000, 72),
+             (480, 640), (31, 200)] * 4
+    frames = [synth.make_frame(synth.SMALL_640x480, 900 + i, w, h)[0]
+              for i, (h, w) in enumerate(sizes)]
+    devs = [torch.from_numpy(f).cuda() for f in frames]
+    uids = [900 + i for i in range(len(frames))]
+    kw = dict(n_hstrips=8, n_vstrips=32, ransac_attempts=64)
+    say("odd sizes, 32 vertical strips")
+    g = run_gpu(est, devs, kw, uids, what=("pts", "res"))
+    for i, f in enumerate(frames):
+        r, p = oracle.estimate(f, oracle_params(**kw), uids[i], with_points=True)
+        assert_points_equal(g["pts"][i:i + 1], [p])
+        assert_results_equal(g["res"][i:i + 1], [r])
+
+
 def test_frame_result_independent_of_batch(torch_dev, est, small_batch):
     torch = torch_dev
     frames, _ = small_batch
