@@ -538,8 +538,14 @@ int ca_server_close(ca_server *server, int32_t stream_id);
 
 /* Submit the next frame of an open stream: `src` holds height rows of
  * 3 width bytes, `row_stride` bytes apart, in device memory
- * (src_is_device = 1) or pinned host memory (0).  It must stay unchanged
- * until the frame is served.  `seq` must increase per stream. */
+ * (src_is_device = 1) or pinned host memory (0), copied into a slot of the
+ * stream's ring when one is free; or in device memory lent to the server
+ * (2): the frame's batch reads it in place, with no ring slot and no copy
+ * (row_stride at most INT32_MAX), and it must stay allocated until the
+ * frame is served.  In every mode `src` must stay unchanged until the frame
+ * is served.  `seq` must increase per stream; a stream's frames are served
+ * in submission order whatever their modes.  CA_E_INVAL for another
+ * src_is_device, a short stride, a closed or unknown stream. */
 int ca_server_submit(ca_server *server, int32_t stream_id, uint64_t seq, const uint8_t *src,
                      int64_t row_stride, int32_t src_is_device);
 

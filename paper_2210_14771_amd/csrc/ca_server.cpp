@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -92,7 +93,7 @@ struct Pending {
     uint64_t seq;
     const uint8_t *src;
     int64_t stride;
-    int32_t is_dev;
+    int32_t is_dev;     // 0 host, 1 device (copied), 2 device lent until served
     int64_t t_submit;
 };
 
@@ -112,8 +113,10 @@ struct Stream {
 struct Entry {                          // one frame from copy to retirement
     Stream *st;
     uint64_t seq;
-    int32_t slot;
+    int32_t slot;                       // ring slot, or -1: read in place
     int64_t t_submit;
+    const uint8_t *src = nullptr;       // a lent frame (slot -1) and its row stride
+    int64_t stride = 0;
 };
 
 struct Batch {                          // one in-flight slot
@@ -196,10 +199,18 @@ size_t stage_batch(ca_server *s, Batch &b, size_t n)
             std::memcpy(tables + k * (size_t)S, e.st->table.data(), sizeof(int32_t) * (size_t)S);
         }
         ca::FrameDev &d = fd[i];
-        d.offset = (int64_t)(e.st->ring_off + (size_t)e.slot * e.st->slot_bytes);
+        if (e.slot >= 0) {
+            d.offset = (int64_t)(e.st->ring_off + (size_t)e.slot * e.st->slot_bytes);
+        } else {
+            // a lent frame: its address relative to the arena the kernels
+            // take as the frames' base (flat device addresses)
+            d.offset = (int64_t)(reinterpret_cast<uintptr_t>(e.src)
+                                 - reinterpret_cast<uintptr_t>(s->arena_mem));
+            aligned = aligned && (d.offset % 16) == 0;
+        }
         d.W = e.st->W;
         d.H = e.st->H;
-        d.rs = 3 * e.st->W;
+        d.rs = e.slot >= 0 ? 3 * e.st->W : (int32_t)e.stride;
         d.table = (int32_t)k * S;
         d.uid = ((uint64_t)(uint32_t)e.st->id << 32) | (e.seq & 0xFFFFFFFFull);
         longest = std::max(longest, std::max(e.st->W, e.st->H));
@@ -279,7 +290,8 @@ int retire(ca_server *s)
             out.t_done_ns = t;
             out.batch_size = (int32_t)b.entries.size();
             s->done.push_back(out);
-            e.st->free_slots.push_back(e.slot);
+            if (e.slot >= 0)
+                e.st->free_slots.push_back(e.slot);
             --e.st->outstanding;
             ++s->n_served;
         }
@@ -310,7 +322,9 @@ void admit(ca_server *s)
 // Copies of submitted frames into free ring slots: frames in device memory
 // go into one batched copy launch per kMaxIngest frames (k_ingest; a lone
 // frame takes the runtime's 2-D copy, measured quicker for one frame),
-// frames in host memory into one 2-D copy each.
+// frames in host memory into one 2-D copy each.  Lent frames are ready at
+// once, read in place; a stream's frames stay in submission order (a lent
+// frame waits behind a copied one that waits for a slot).
 int ingest(ca_server *s)
 {
     ca::IngestArgs batch;
@@ -333,8 +347,17 @@ int ingest(ca_server *s)
     for (Stream *st : s->order) {
         if (!st->admitted)
             continue;
-        while (!st->queue.empty() && !st->free_slots.empty()) {
+        while (!st->queue.empty()) {
             const Pending p = st->queue.front();
+            if (p.is_dev == 2) {
+                // lent: read in place by its batch, no slot and no copy
+                st->queue.pop_front();
+                s->ready.push_back({st, p.seq, -1, p.t_submit, p.src, p.stride});
+                ++st->outstanding;
+                continue;
+            }
+            if (st->free_slots.empty())
+                break;
             st->queue.pop_front();
             const int32_t slot = st->free_slots.back();
             st->free_slots.pop_back();
@@ -353,7 +376,7 @@ int ingest(ca_server *s)
                                         s->compute) != hipSuccess) {
                 return CA_E_DEVICE;
             }
-            s->ready.push_back({st, p.seq, slot, p.t_submit});
+            s->ready.push_back({st, p.seq, slot, p.t_submit, nullptr, 0});
             ++st->outstanding;
         }
     }
@@ -607,11 +630,12 @@ int ca_server_submit(ca_server *s, int32_t id, uint64_t seq, const uint8_t *src,
     if (it == s->streams.end() || it->second->closing)
         return CA_E_INVAL;
     Stream *st = it->second;
-    if (stride < 3 * (int64_t)st->W || (st->any_seq && seq <= st->last_seq))
+    if (stride < 3 * (int64_t)st->W || (st->any_seq && seq <= st->last_seq)
+        || src_is_device < 0 || src_is_device > 2 || (src_is_device == 2 && stride > INT32_MAX))
         return CA_E_INVAL;
     st->any_seq = true;
     st->last_seq = seq;
-    st->queue.push_back({seq, src, stride, src_is_device ? 1 : 0, now_ns()});
+    st->queue.push_back({seq, src, stride, src_is_device, now_ns()});
     ++s->n_submitted;
     return CA_OK;
 }

@@ -59,11 +59,12 @@ class Server:
     def close_stream(self, stream_id: int) -> None:
         N.check(N.lib().ca_server_close(self._s, stream_id), "ca_server_close")
 
-    def submit(self, stream_id: int, seq: int, frame) -> None:
-        """`frame`: a device uint8 [H, W, 3] tensor (kept alive by the caller
-        until served)."""
+    def submit(self, stream_id: int, seq: int, frame, lend: bool = False) -> None:
+        """`frame`: a device uint8 [H, W, 3] tensor (kept alive and unchanged
+        by the caller until served).  With `lend` the server reads it in
+        place instead of copying it into the stream's ring."""
         N.check(N.lib().ca_server_submit(self._s, stream_id, seq, C.c_void_p(frame.data_ptr()),
-                                         frame.stride(0), 1), "ca_server_submit")
+                                         frame.stride(0), 2 if lend else 1), "ca_server_submit")
 
     def step(self) -> list:
         n = C.c_int32()
@@ -149,7 +150,7 @@ def make_streams(n_streams: int = 48, frames_per_stream: int = 16, duration_s: f
 
 
 def run(server: Server, streams, realtime: bool = True, only=None, timeout_s: float = 120.0,
-        progress=None):
+        progress=None, lend: bool = False):
     """Submit every stream's frames at their arrival times (or as fast as
     possible), step the server until all are served; returns the served
     records and the wall time.  Raises if the frames are not all served
@@ -179,7 +180,7 @@ def run(server: Server, streams, realtime: bool = True, only=None, timeout_s: fl
         while i < len(events) and (not realtime or events[i][0] <= now):
             _, sid, k = events[i]
             st = by_id[sid]
-            server.submit(sid, k, st.frames[k % len(st.frames)])
+            server.submit(sid, k, st.frames[k % len(st.frames)], lend)
             i += 1
         served += [served_record(s) for s in server.step()]
         if now > timeout_s:

@@ -67,7 +67,9 @@ def run_benchmark(n_streams: int = 48, seconds: float = 0.4, frames_per_stream: 
     frame submitted at its arrival time, the server stepped until every
     frame is served.  Then a second server takes the same frames as one
     backlog (every frame submitted at once, each stream's ring admitting two
-    at a time): the throughput of continuous batching under full load."""
+    at a time): the throughput of continuous batching under full load; and
+    a third the backlog with every frame lent (read in place, no ring
+    copies, batches limited by max_batch only)."""
     import torch
 
     if log:
@@ -114,6 +116,17 @@ def run_benchmark(n_streams: int = 48, seconds: float = 0.4, frames_per_stream: 
         srv.close()
         rec["backlog"] = dict(serve.latency_summary(served_b, wall_b),
                               batches=stats_b["batches"])
+        # the same backlog with the frames lent to the server: read in
+        # place, no ring copies
+        srv = serve.Server(est, cfg)
+        if log:
+            log(f"serving ({name}, backlog, lent frames)")
+        served_l, wall_l = serve.run(srv, streams, realtime=False, timeout_s=60, progress=log,
+                                     lend=True)
+        stats_l = srv.stats()
+        srv.close()
+        rec["backlog_lent"] = dict(serve.latency_summary(served_l, wall_l),
+                                   batches=stats_l["batches"])
         line[name] = rec
     torch.cuda.synchronize()
     est.close()

@@ -649,7 +649,9 @@ void serve(ca_ctx *ctx, const Sim &sim, const ca_server_config &cfg, bool realti
             const Frame &f = sim.arrivals[next++];
             const int32_t W = sim.shapes[(size_t)f.stream].first;
             const uint8_t *p = src[(size_t)(f.stream % 3)];
-            CHECK(ca_server_submit(srv, f.stream, f.seq, p, 3 * (int64_t)W, 1) == CA_OK);
+            // every other frame of a stream lent (read in place), the rest copied
+            CHECK(ca_server_submit(srv, f.stream, f.seq, p, 3 * (int64_t)W, f.seq % 2 ? 1 : 2)
+                  == CA_OK);
         }
         step(srv, got);
         now += dt;

@@ -243,3 +243,61 @@ def test_learned_scorers_served_equal_the_batch_api(torch_dev, streams):
             want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
             assert r["result"] == want, (scorer, r["stream"], r["seq"])
     est.close()
+
+
+def test_lent_frames_read_in_place(torch_dev, streams):
+    """Frames lent to the server (read in place, no ring slot) mixed with
+    copied ones in each stream, padded rows among them: each stream's frames
+    are served in submission order, each result equals the batch API's on
+    the same frame and uid, and results and filtered circles equal those of
+    the same backlog with every frame copied."""
+    torch = torch_dev
+    est = api.Estimator(0)
+    src = [streams[0], streams[1]]                     # 720p and 1080p
+    ids = [200, 201, 202, 203]
+    frames = {}
+    for k, sid in enumerate(ids):
+        st = src[k % 2]
+        base = st.frames[1]
+        if k < 2:                                      # padded rows: a view into a wider image
+            wide = torch.zeros((st.height, st.width + 5, 3), dtype=torch.uint8, device="cuda")
+            wide[:, :st.width].copy_(base)
+            f = wide[:, :st.width]
+        else:
+            f = base
+        frames[sid] = f
+    torch.cuda.synchronize()
+
+    def serve_all(lend_of):
+        srv = serve.Server(est, serve.server_config(max_batch=16, **KW))
+        for k, sid in enumerate(ids):
+            assert srv.open(sid, src[k % 2].width, src[k % 2].height)
+        for seq in range(6):
+            for sid in ids:
+                srv.submit(sid, seq, frames[sid], lend_of(sid, seq))
+        served = []
+        for _ in range(100000):
+            served += [serve.served_record(s) for s in srv.step()]
+            if len(served) == 6 * len(ids):
+                break
+        srv.close()
+        assert len(served) == 6 * len(ids)
+        return served
+
+    say("lent and copied frames in one backlog")
+    mixed = serve_all(lambda sid, seq: (seq + sid) % 2 == 0)
+    copied = serve_all(lambda sid, seq: False)
+    for sid in ids:
+        seqs = [r["seq"] for r in mixed if r["stream"] == sid]
+        assert seqs == sorted(seqs) == list(range(6)), sid
+    by = {_key(r): r for r in copied}
+    for r in mixed:
+        assert r["result"] == by[_key(r)]["result"], _key(r)
+        assert r["filtered"] == by[_key(r)]["filtered"], _key(r)
+        uid = (r["stream"] << 32) | r["seq"]
+        res = est.estimate_area(frames[r["stream"]], api.default_params(**KW), [uid])
+        torch.cuda.synchronize()
+        raw = res.raw.cpu().numpy()[0]
+        want = tuple(raw[:4].view(np.float32)) + tuple(int(v) for v in raw[4:])
+        assert r["result"] == want, _key(r)
+    est.close()
