@@ -764,6 +764,11 @@ void scenario_memory_wait()
     for (int k = 0; k < 4; ++k)
         CHECK(ca_server_open(srv, ids[k], 1920, 1080, &adm[k]) == CA_OK);
     CHECK(adm[0] && adm[1] && !adm[2] && !adm[3]);
+    // submission modes other than host (0), device (1) and lent (2), and a
+    // lent frame's stride beyond 32 bits, are rejected before any state changes
+    CHECK(ca_server_submit(srv, ids[0], 0, src[1], 3 * 1920, 3) == CA_E_INVAL);
+    CHECK(ca_server_submit(srv, ids[0], 0, src[1], 3 * 1920, -1) == CA_E_INVAL);
+    CHECK(ca_server_submit(srv, ids[0], 0, src[1], (int64_t)1 << 32, 2) == CA_E_INVAL);
     for (int k = 0; k < 4; ++k)
         for (uint64_t q = 0; q < 3; ++q)
             CHECK(ca_server_submit(srv, ids[k], q, src[1], 3 * 1920, 1) == CA_OK);
